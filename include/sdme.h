@@ -1,0 +1,343 @@
+/*
+ * libsdme -- SDME high-order FEM hot path for AMD MI355X (gfx950).
+ *
+ * Element-by-element neo-Hookean internal force and tangent-stiffness action
+ * on structured tensor-product hexahedra, evaluated at Gauss points with the
+ * one-dimensional SDME bases of Dias, Suzuki, Valente & Bittencourt,
+ * "Simulation of non-linear structural elastodynamic and impact problems using
+ * minimum energy and simultaneous diagonalization high-order bases"
+ * (arXiv 2104.13466), plus the Jacobi-preconditioned CG, static Newton,
+ * Newmark-Newton and central-difference drivers built on them.
+ *
+ * Conventions (all entry points):
+ *  - Plain C ABI.  Every function returns an int status (SDME_OK = 0 or a
+ *    negative SDME_E* code); no exception or abort crosses the boundary.
+ *    Arguments are validated on the host before any launch.
+ *  - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *    pointers are host memory owned by the caller.  The library never frees a
+ *    caller buffer.  sdme_create allocates one small device block (reduction
+ *    partials and solver scalars, O(number of elements) bytes) and a few bytes
+ *    of pinned host memory, released by sdme_destroy.  Large scratch (solver
+ *    vectors, linearisation state) is passed in by the caller as a workspace
+ *    of at least sdme_workspace_bytes() bytes.
+ *  - Vectors are structure-of-arrays [3][Nn]: component c of global slot g at
+ *    index c*Nn + g.  The structured slot grid has Nd = nd*P+1 slots per
+ *    direction, numbered x fastest: g = (iz*Ny + iy)*Nx + ix.  Element
+ *    (ex,ey,ez) with local mode (a,b,c) (tensor indices of Eq.
+ *    ProdTensorialHexaedro) owns slot (ex*P+a, ey*P+b, ez*P+c); element index
+ *    e = (ez*ny + ey)*nx + ex, local index l = (c*(P+1) + b)*(P+1) + a.
+ *  - prec selects the storage and arithmetic type of the vectors passed as
+ *    void*: SDME_FP64 -> double, SDME_FP32 -> float.  Reductions (dot
+ *    products, energies) always accumulate in double.
+ *  - stream is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *    are asynchronous on that stream unless documented as synchronising
+ *    (solvers and drivers read convergence scalars back and return after the
+ *    solve; their stats are valid on return).
+ *  - Dirichlet DOFs (faces/components set in sdme_mesh_desc.dirichlet) carry
+ *    their prescribed values inside displacement vectors.  With
+ *    SDME_MASK_BC, operators treat constrained DOFs of their input direction
+ *    as zero and write zero to constrained outputs.
+ */
+#ifndef SDME_H
+#define SDME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define SDME_OK 0
+#define SDME_EINVAL (-1)      /* bad argument (checked before any launch)     */
+#define SDME_ENOMEM (-2)      /* workspace too small / allocation failed      */
+#define SDME_EDEVICE (-3)     /* HIP runtime error                            */
+#define SDME_EEIG (-4)        /* basis eigensolve / factorisation failed      */
+#define SDME_EJAC (-5)        /* det F <= 0 at a Gauss point                  */
+#define SDME_ENOCONV (-6)     /* iteration limit reached before tolerance     */
+#define SDME_EBREAKDOWN (-7)  /* CG breakdown: p^T A p <= 0                   */
+#define SDME_ENAN (-8)        /* non-finite value in a residual or scalar     */
+
+const char *sdme_status_string(int status);
+
+/* ------------------------------------------------------------- 1D bases */
+#define SDME_BASIS_NODAL 0   /* Lagrange on GLL points (Eq. lagrangian)           */
+#define SDME_BASIS_MODAL 1   /* standard Jacobi(1,1) modal "ST" (Eq. BasePadrao1D) */
+#define SDME_BASIS_SDME_M 2  /* SD + minimum energy in the L2 norm                */
+#define SDME_BASIS_SDME_K 3  /* SD + minimum energy in the energy norm            */
+#define SDME_BASIS_SDME_H 4  /* SD + minimum energy in the norm of K + lambda M   */
+
+/*
+ * sdme_basis_build -- construct a 1D basis of order P (Section 2) and tabulate
+ * it at the Q Gauss-Legendre points.
+ *   SD step (Eqs. diagMassa, L, diagL, Y, ParametroK) with parameter k in
+ *   [0,1]; ME step (Eqs. ExtensaoMEmassa, alphaMassa, alphaRigidez, alphaKN)
+ *   with lambda_h for SDME-H.  Internal modes are ordered by ascending
+ *   eigenvalue Lambda_S and signed so that their derivative at xi = -1 is
+ *   positive.  Slot order: 0 = left vertex mode, 1..P-1 internal, P = right
+ *   vertex mode.
+ * Outputs (host, row-major, any may be NULL):
+ *   x[Q], w[Q]          Gauss points and weights on [-1,1]
+ *   B[Q][P+1], D[Q][P+1] values and derivatives of the slots at x
+ *   M1, K1 [(P+1)^2]    1D mass and stiffness in slot order
+ *   lambda_s[P-1]       eigenvalues Lambda_S (SDME kinds; zeros otherwise)
+ * Limits: 1 <= P <= 10, P+1 <= Q <= 16, 0 <= k <= 1, lambda_h >= 0.
+ * Errors: SDME_EINVAL for limits, SDME_EEIG if an eigensolve or Cholesky
+ * factorisation fails.
+ */
+int sdme_basis_build(int P, int Q, int kind, double k, double lambda_h, double *x, double *w,
+                     double *B, double *D, double *M1, double *K1, double *lambda_s);
+
+/* Evaluate the same basis at npts arbitrary points (host arrays
+ * V[npts][P+1], dV[npts][P+1]; dV may be NULL). */
+int sdme_basis_eval(int P, int kind, double k, double lambda_h, int npts, const double *pts,
+                    double *V, double *dV);
+
+/* ------------------------------------------------------------ mesh/context */
+typedef struct sdme_ctx sdme_ctx;
+
+typedef struct {
+  int nx, ny, nz;     /* hexahedra per direction (>= 1)                       */
+  int P;              /* polynomial order, 1..8                               */
+  int Q;              /* Gauss-Legendre points per direction: must be P+2      */
+  int basis;          /* SDME_BASIS_*                                          */
+  double k;           /* SD parameter k (Eq. Y), paper value 0.5               */
+  double lambda_h;    /* SDME-H parameter lambda (Eq. EffectiveStiffness_lambda), paper 100 */
+  double h[3];        /* element edge lengths (affine boxes)                   */
+  double origin[3];   /* coordinates of the box corner                         */
+  uint32_t dirichlet; /* bit (face*3 + comp): faces 0 x=0, 1 x=max, 2 y=0, 3 y=max, 4 z=0, 5 z=max */
+} sdme_mesh_desc;
+
+/* Create a context for a structured box mesh on the current HIP device.  The
+ * basis is built on the host (sdme_basis_build) and its tables are uploaded
+ * to the context's device block.  Errors: SDME_EINVAL, SDME_EEIG,
+ * SDME_EDEVICE. */
+int sdme_create(const sdme_mesh_desc *desc, sdme_ctx **out);
+int sdme_destroy(sdme_ctx *ctx);
+
+/* out[0] = Nn (slots per component), out[1] = E (elements),
+ * out[2] = Gauss points (E*Q^3), out[3] = words of linearisation state per
+ * Gauss point (10: F^-1 and mu - lambda ln J). */
+int sdme_sizes(const sdme_ctx *ctx, int64_t out[4]);
+
+/* Element-to-global map: host_out[e*(P+1)^3 + l] = global slot (Eq.
+ * ProdTensorialHexaedro indices; topological association of Section 2). */
+int sdme_gather_indices(const sdme_ctx *ctx, int32_t *host_out);
+
+/* host_out[c*Nn + g] = 1 if DOF (c,g) is constrained, else 0. */
+int sdme_dirichlet_flags(const sdme_ctx *ctx, uint8_t *host_out);
+
+/* Coefficients of the affine field u(X) = a + G X (G row-major 3x3) in the
+ * tensor-product basis, written to host_out[3*Nn] (the expansion is exact: the
+ * 1D expansions of 1 and xi, combined per element with X = Xc + (h/2) xi). */
+int sdme_affine_field(const sdme_ctx *ctx, const double a[3], const double G[9],
+                      double *host_out);
+
+/* --------------------------------------------------------------- operators */
+#define SDME_FP64 0
+#define SDME_FP32 1
+
+#define SDME_MASK_BC 1   /* zero constrained inputs (direction) and outputs   */
+#define SDME_CHECK_JAC 2 /* synchronise and return SDME_EJAC if det F <= 0    */
+
+/* Per-element Lame parameters (device, double[E]) and density. */
+typedef struct {
+  const double *mu;
+  const double *lam;
+  double rho;
+} sdme_material;
+
+/*
+ * sdme_internal_force -- R(u) = sum_e sum_q w_q detJ P(F) : grad N
+ * (second term of Eq. material virtual work; compressible neo-Hookean,
+ * Eq. hyperelastic strain energy / second Piola-Kirchhoff relation, with
+ * P = F S).  u, R: dev [3][Nn] of type prec; R is overwritten.
+ * state (dev, nullable): if given, the linearisation state of u is written,
+ * layout [E][10][Q^3] of type prec (F^-1 row-major, then mu - lambda ln J).
+ * flags: SDME_MASK_BC masks R on constrained DOFs (u is never masked);
+ * SDME_CHECK_JAC synchronises and reports det F <= 0.
+ */
+int sdme_internal_force(sdme_ctx *ctx, const sdme_material *mat, int prec, const void *u,
+                        void *R, void *state, int flags, void *stream);
+
+/* Write only the linearisation state of u (see sdme_internal_force). */
+int sdme_linearize(sdme_ctx *ctx, const sdme_material *mat, int prec, const void *u,
+                   void *state, int flags, void *stream);
+
+/*
+ * sdme_tangent_apply -- y = (K_T(u_lin) + mass_shift * M) v, K_T the
+ * derivative of R (linearisation, Eq. directional derivative / effective
+ * stiffness) and M the consistent mass rho int N N (so mass_shift = b1 gives
+ * the Newmark matrix b1 M + K_T).  Exactly one of u_lin (recompute F at every
+ * Gauss point) and state (stored linearisation from sdme_linearize) is
+ * non-NULL.  v, y: dev [3][Nn] of type prec; y is overwritten.
+ */
+int sdme_tangent_apply(sdme_ctx *ctx, const sdme_material *mat, int prec, const void *u_lin,
+                       const void *state, double mass_shift, const void *v, void *y, int flags,
+                       void *stream);
+
+/* y = rho M v (consistent mass, inertia term of Eq. material virtual work). */
+int sdme_mass_apply(sdme_ctx *ctx, double rho, int prec, const void *v, void *y, int flags,
+                    void *stream);
+
+/* d = diag(K_T + mass_shift M) from a stored linearisation state (Jacobi
+ * preconditioner of the element-by-element diagonal PCG, Section 5).  With
+ * SDME_MASK_BC constrained entries are set to 1. */
+int sdme_jacobi_diag(sdme_ctx *ctx, const sdme_material *mat, int prec, const void *state,
+                     double mass_shift, void *d, int flags, void *stream);
+
+/* Strain energy sum_e sum_q w_q detJ Psi(F(u)) -> *host_out (synchronises). */
+int sdme_strain_energy(sdme_ctx *ctx, const sdme_material *mat, const double *u,
+                       double *host_out, void *stream);
+
+/* Dead traction t (reference configuration) on a box face: f += scale *
+ * int_face N t dA, surface Gauss rule with P+1 points per direction.  f: dev
+ * double [3][Nn], accumulated. */
+int sdme_face_traction(sdme_ctx *ctx, int face, const double t[3], double scale, double *f,
+                       void *stream);
+
+/* Rigid plane z = z0 (normal +z) below face z=0: gap g = Z + u_z - z0 at the
+ * face Gauss points (P+1 per direction, the paper's contact rule), penalty
+ * force f_z += int N eps max(-g,0) dA (accumulated into f).  If energy_host is
+ * non-NULL the penalty energy 1/2 eps int min(g,0)^2 dA is returned there
+ * (synchronises). */
+typedef struct {
+  double eps; /* penalty per unit area */
+  double z0;  /* plane height          */
+} sdme_contact;
+
+int sdme_penalty_plane(sdme_ctx *ctx, const sdme_contact *c, const double *u, double *f,
+                       double *energy_host, void *stream);
+
+/* Sensitivity of R to the element Lame parameters contracted with w:
+ * g_mu[e] += scale * sum_q w_q detJ (F - F^-T) : grad w,
+ * g_lam[e] += scale * sum_q w_q detJ lnJ F^-T : grad w  (dev double[E]). */
+int sdme_material_grad_accumulate(sdme_ctx *ctx, const double *u, const double *w, double scale,
+                                  double *g_mu, double *g_lam, void *stream);
+
+/* ----------------------------------------------------------------- solvers */
+typedef struct {
+  int status;         /* SDME_OK or error                                     */
+  int iterations;     /* PCG iterations (all inner iterations in mixed mode)  */
+  int outer;          /* FP64 defect-correction sweeps (mixed mode)           */
+  int newton;         /* Newton iterations                                    */
+  int mass_iterations;/* PCG iterations of mass solves (explicit, adjoint)    */
+  int pad;
+  double rel_residual;/* final ||b - A x|| / ||b|| (FP64)                      */
+  double newton_rel;  /* final ||psi|| / ||psi_0||                             */
+  double time_ms;     /* wall time of the call                                */
+} sdme_stats;
+
+#define SDME_OP_PCG 0
+#define SDME_OP_NEWTON 1
+#define SDME_OP_NEWMARK 2
+#define SDME_OP_EXPLICIT 3
+#define SDME_OP_ADJOINT 4
+
+/* Workspace bytes needed by a solver/driver entry point with the given prec
+ * (SDME_FP64 or SDME_FP32 = mixed FP32 inner / FP64 outer). */
+int sdme_workspace_bytes(const sdme_ctx *ctx, int op, int prec, size_t *bytes);
+
+/*
+ * sdme_jacobi_pcg -- solve (K_T(u_lin) + mass_shift M) x = b on the free DOFs
+ * by conjugate gradients with the diagonal preconditioner (the paper's CGD /
+ * element-by-element diagonal PCG, Section 5).  b, x: dev double [3][Nn]
+ * (x overwritten, zero on constrained DOFs; b masked internally).  Stops when
+ * ||b - A x||_2 <= rtol ||b||_2.
+ * prec = SDME_FP64: FP64 vectors, state and operator.
+ * prec = SDME_FP32: mixed precision -- FP32 inner PCG (FP32 state, operator
+ * and vectors, FP64 dots) to inner_rtol, FP64 defect correction r = b - A x
+ * with the FP64 operator until rtol.
+ * mass_only != 0 solves with the mass matrix alone (K_T omitted, u_lin unused).
+ * Synchronises.  Errors: SDME_ENOCONV (maxit), SDME_EBREAKDOWN, SDME_EJAC,
+ * SDME_ENOMEM (ws_bytes too small).
+ */
+int sdme_jacobi_pcg(sdme_ctx *ctx, const sdme_material *mat, int prec, const double *u_lin,
+                    double mass_shift, int mass_only, const double *b, double *x, double rtol,
+                    int maxit, double inner_rtol, sdme_stats *stats, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* Static Newton-Raphson for R(u) = f_ext (f_ext nullable = 0): K_T du = psi,
+ * stop at ||psi||/||psi_0|| <= newton_rtol.  u: dev double [3][Nn], in/out
+ * (prescribed values on constrained DOFs are kept).  Synchronises. */
+int sdme_newton_static(sdme_ctx *ctx, const sdme_material *mat, int prec, double *u,
+                       const double *f_ext, double newton_rtol, double pcg_rtol, int max_newton,
+                       int max_pcg, sdme_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * sdme_newmark_newton_step -- one Newmark step (Section 4, implicit time
+ * integration) with Newton iterations:
+ *   psi = P_{n+1} - R(u) - M (b1 (u - u_n) - b2 v_n - b3 a_n),
+ *   (b1 M + K_T) du = psi,  b1 = 1/(beta dt^2), b2 = 1/(beta dt),
+ *   b3 = 1/(2 beta) - 1;  then a_{n+1} = b1 (u - u_n) - b2 v_n - b3 a_n,
+ *   v_{n+1} = v_n + dt ((1-gamma) a_n + gamma a_{n+1}).
+ * u, v, a: dev double [3][Nn], in (step n) / out (step n+1).  f_next
+ * nullable.  Synchronises.
+ */
+int sdme_newmark_newton_step(sdme_ctx *ctx, const sdme_material *mat, int prec, double *u,
+                             double *v, double *a, const double *f_next, double dt, double beta,
+                             double gamma, double newton_rtol, double pcg_rtol, int max_newton,
+                             int max_pcg, sdme_stats *stats, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/*
+ * sdme_explicit_step -- central difference (Section 4, explicit time
+ * integration, Eq. Motion_explicit2): u_next = 2 u_cur - u_prev + dt^2 a with
+ * M a = P - R(u_cur) + f_c(u_cur) solved by Jacobi-PCG on the mass matrix to
+ * mass_rtol (f_ext and contact nullable).  prec_force selects the precision
+ * of the internal-force evaluation (the update and mass solve are FP64).
+ * If u_prev == NULL the start step is taken: u_next = u_cur + dt v0 +
+ * dt^2/2 a_0 with v0 passed in place of u_prev through v0_if_start.
+ * Synchronises (mass solve).
+ */
+int sdme_explicit_step(sdme_ctx *ctx, const sdme_material *mat, int prec_force,
+                       const double *u_prev, const double *u_cur, double *u_next,
+                       const double *v0_if_start, const double *f_ext, double dt,
+                       const sdme_contact *contact, double mass_rtol, sdme_stats *stats, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Energies at step n: out[0] = 1/2 v^T M v with v = (u_next - u_prev)/(2 dt),
+ * out[1] = strain energy of u_cur, out[2] = penalty energy (0 without
+ * contact).  Synchronises. */
+int sdme_energies(sdme_ctx *ctx, const sdme_material *mat, const double *u_prev,
+                  const double *u_cur, const double *u_next, double dt,
+                  const sdme_contact *contact, double out_host[3], void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* Largest eigenvalue of M^-1 (K_T(u_lin) + K_c) by power iteration from the
+ * caller's start vector x0 (dev double [3][Nn]); K_c is the penalty
+ * stiffness eps int N_z N_z dA on face z=0 when contact != NULL (all face
+ * points taken as active).  Used for the CFL step dt = cfl * 2 / sqrt(lambda).
+ * Synchronises. */
+int sdme_lambda_max(sdme_ctx *ctx, const sdme_material *mat, const double *u_lin,
+                    const sdme_contact *contact, const double *x0, int iters, double mass_rtol,
+                    double *lambda_host, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * sdme_explicit_adjoint_step -- one step of the discrete adjoint of the
+ * unloaded central-difference rollout (no contact) for J = 1/2 ||u_K - u*||^2:
+ *   w = M^-1 lam_next;
+ *   g_mu, g_lam += scale * dR(u_n)/d(mu, lam)^T w, scale = -dt^2 (n >= 1) or
+ *   -dt^2/2 (n = 0, first != 0);
+ *   if !first: lam_out = 2 lam_next - dt^2 K_T(u_n) w - lam_next2.
+ * All vectors dev double [3][Nn]; g_mu, g_lam dev double [E].  Synchronises.
+ */
+int sdme_explicit_adjoint_step(sdme_ctx *ctx, const sdme_material *mat, const double *u_n,
+                               const double *lam_next, const double *lam_next2, double *lam_out,
+                               double dt, int first, double mass_rtol, double *g_mu,
+                               double *g_lam, sdme_stats *stats, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/* lam_out = mask (u - target); *J_host = 1/2 ||lam_out||^2 (synchronises). */
+int sdme_misfit(sdme_ctx *ctx, const double *u, const double *target, double *lam_out,
+                double *J_host, void *stream);
+
+/* y = alpha x + beta y on dev double [n] (vector update used by drivers). */
+int sdme_axpby(sdme_ctx *ctx, int64_t n, double alpha, const double *x, double beta, double *y,
+               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDME_H */

@@ -1,0 +1,115 @@
+// Runtime dispatch on the polynomial order to the per-order element-kernel
+// wrappers (each order is compiled in its own translation unit).
+#include <hip/hip_runtime.h>
+
+#include "sdme_device.h"
+#include "sdme_launch.h"
+
+namespace sdme {
+
+template <int P, typename T>
+int launch_force_t(const MeshK<T> &, const double *, const double *, const T *, T *, T *, int,
+                   hipStream_t);
+template <int P, typename T>
+int launch_tangent_t(const MeshK<T> &, const double *, const double *, const T *, const T *, T,
+                     const T *, T *, int, Reduce, int, const int *, hipStream_t);
+template <int P, typename T>
+int launch_mass_t(const MeshK<T> &, T, const T *, T *, int, Reduce, int, const int *, hipStream_t);
+template <int P, typename T>
+int launch_diag_t(const MeshK<T> &, const double *, const double *, const T *, T, T *, int,
+                  hipStream_t);
+template <int P>
+int launch_energy_t(const MeshK<double> &, const double *, const double *, const double *, Reduce,
+                    hipStream_t);
+template <int P>
+int launch_matgrad_t(const MeshK<double> &, const double *, const double *, double, double *,
+                     double *, hipStream_t);
+
+#define SDME_DISPATCH(P_, CALL) \
+  switch (P_) {                 \
+    case 1: return CALL(1);     \
+    case 2: return CALL(2);     \
+    case 3: return CALL(3);     \
+    case 4: return CALL(4);     \
+    case 5: return CALL(5);     \
+    case 6: return CALL(6);     \
+    case 7: return CALL(7);     \
+    case 8: return CALL(8);     \
+    default: return -2;         \
+  }
+
+template <typename T>
+int launch_force(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *u, T *R,
+                 T *state, int mask, hipStream_t st) {
+#define C(p) launch_force_t<p, T>(m, mu, lam, u, R, state, mask, st)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+template <typename T>
+int launch_tangent(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
+                   const T *state, T msr, const T *v, T *y, int mask, Reduce red, int do_red,
+                   const int *skip, hipStream_t st) {
+#define C(p) launch_tangent_t<p, T>(m, mu, lam, ulin, state, msr, v, y, mask, red, do_red, skip, st)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+template <typename T>
+int launch_mass(int P, const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red,
+                int do_red, const int *skip, hipStream_t st) {
+#define C(p) launch_mass_t<p, T>(m, rho, v, y, mask, red, do_red, skip, st)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+template <typename T>
+int launch_diag(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *state,
+                T msr, T *d, int mask, hipStream_t st) {
+#define C(p) launch_diag_t<p, T>(m, mu, lam, state, msr, d, mask, st)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+int launch_energy(int P, const MeshK<double> &m, const double *mu, const double *lam,
+                  const double *u, Reduce red, hipStream_t st) {
+#define C(p) launch_energy_t<p>(m, mu, lam, u, red, st)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double *w, double scale,
+                   double *gm, double *gl, hipStream_t st) {
+#define C(p) launch_matgrad_t<p>(m, u, w, scale, gm, gl, st)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+
+int elem_blocks(int P, int word, int E) {
+  int ne = 1;
+  switch (P * 10 + (word == 8 ? 1 : 0)) {
+#define NEC(p)                                                        \
+  case p * 10 + 1: ne = Dims<p, p + 2, 8>::NE; break;                \
+  case p * 10 + 0: ne = Dims<p, p + 2, 4>::NE; break;
+    NEC(1) NEC(2) NEC(3) NEC(4) NEC(5) NEC(6) NEC(7) NEC(8)
+#undef NEC
+    default: ne = 1;
+  }
+  return (E + ne - 1) / ne;
+}
+
+template int launch_force<double>(int, const MeshK<double> &, const double *, const double *,
+                                  const double *, double *, double *, int, hipStream_t);
+template int launch_force<float>(int, const MeshK<float> &, const double *, const double *,
+                                 const float *, float *, float *, int, hipStream_t);
+template int launch_tangent<double>(int, const MeshK<double> &, const double *, const double *,
+                                    const double *, const double *, double, const double *,
+                                    double *, int, Reduce, int, const int *, hipStream_t);
+template int launch_tangent<float>(int, const MeshK<float> &, const double *, const double *,
+                                   const float *, const float *, float, const float *, float *,
+                                   int, Reduce, int, const int *, hipStream_t);
+template int launch_mass<double>(int, const MeshK<double> &, double, const double *, double *,
+                                 int, Reduce, int, const int *, hipStream_t);
+template int launch_mass<float>(int, const MeshK<float> &, float, const float *, float *, int,
+                                Reduce, int, const int *, hipStream_t);
+template int launch_diag<double>(int, const MeshK<double> &, const double *, const double *,
+                                 const double *, double, double *, int, hipStream_t);
+template int launch_diag<float>(int, const MeshK<float> &, const double *, const double *,
+                                const float *, float, float *, int, hipStream_t);
+
+}  // namespace sdme

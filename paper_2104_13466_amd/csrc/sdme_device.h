@@ -1,0 +1,200 @@
+// Device-side building blocks of libsdme (gfx950, wave64).
+//
+// Element kernels use a Q x Q thread slab per hexahedron: thread (i1, i2)
+// owns the Gauss-point column (q1 = i1, q2 = i2, q3 = 0..Q-1).  Contractions
+// along xi1 and xi2 go through LDS; the contraction along xi3, the pointwise
+// constitutive update and the transposed xi3 contraction stay in registers.
+// Several elements share a block of at most 256 threads (NE = 256 / Q^2).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sdme {
+
+template <int P_, int Q_, int WORD>
+struct Dims {
+  static constexpr int P = P_, Q = Q_, n = P_ + 1;
+  static constexpr int n3 = n * n * n;
+  static constexpr int QQ = Q * Q;
+  // LDS words per element: region A holds the gathered component (n^3) in the
+  // forward pass or the xi3-contracted fluxes g1..g3 (3 n Q^2) in the
+  // transpose; region B holds the xi1 partial sums (2 n^2 Q).
+  static constexpr int SA = (n3 > 3 * n * QQ) ? n3 : 3 * n * QQ;
+  static constexpr int SB = 2 * n * n * Q;
+  static constexpr int SE = SA + SB;
+  // elements per block: at most 256 threads and 56 KiB of element LDS
+  static constexpr int NE_T = (256 / QQ) > 0 ? (256 / QQ) : 1;
+  static constexpr int NE_L = (57344 / (SE * WORD)) > 0 ? (57344 / (SE * WORD)) : 1;
+  static constexpr int NE = NE_T < NE_L ? NE_T : NE_L;
+  static constexpr int NT = NE * QQ;
+  // tables: B, D (Q n), W (Q), B2, D2, BD (Q n), Bf (n n), Wf (n)
+  static constexpr int TB = 0, TD = Q * n, TW = 2 * Q * n, TB2 = 2 * Q * n + Q,
+                       TD2 = TB2 + Q * n, TBD = TD2 + Q * n, TBF = TBD + Q * n,
+                       TWF = TBF + n * n, TSIZE = TWF + n;
+};
+
+// Mesh parameters passed by value to every kernel.
+template <typename T>
+struct MeshK {
+  int nx, ny, nz, E;
+  int Nx, Ny, Nz, Nn;
+  uint32_t bc;   // Dirichlet bits (face*3 + comp)
+  T ih[3];       // 2 / h_J  (reference-to-physical derivative scale)
+  T detJ;        // h_x h_y h_z / 8
+  const T *tab;  // device basis tables (layout of Dims)
+  int *flag;     // device status word: set to 1 when det F <= 0
+};
+
+// Deterministic block reduction target: each block writes a partial, the last
+// block to finish sums all partials in block order into *result.
+struct Reduce {
+  double *partials;
+  unsigned *counter;
+  double *result;
+};
+
+__device__ __forceinline__ bool is_constrained(uint32_t bc, int comp, int ix, int iy, int iz,
+                                               int Nx, int Ny, int Nz) {
+  uint32_t m = bc >> comp;
+  return ((m & 1u) && ix == 0) || (((m >> 3) & 1u) && ix == Nx - 1) ||
+         (((m >> 6) & 1u) && iy == 0) || (((m >> 9) & 1u) && iy == Ny - 1) ||
+         (((m >> 12) & 1u) && iz == 0) || (((m >> 15) & 1u) && iz == Nz - 1);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block-wide sum of v (all threads call); returns the block total in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *s_red) {
+  constexpr int NW = (NT + 63) / 64;
+  v = wave_sum(v);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s_red[wid] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NW; i++) t += s_red[i];
+  return t;
+}
+
+// Finish a deterministic grid reduction: thread 0 of each block passes its
+// block total; the last block sums all partials in order.
+template <int NT>
+__device__ __forceinline__ void grid_reduce_finish(double block_total, Reduce r, double *s_red,
+                                                   int nblocks) {
+  __shared__ bool s_last;
+  if (threadIdx.x == 0) {
+    r.partials[blockIdx.x] = block_total;
+    __threadfence();
+    unsigned prev = atomicAdd(r.counter, 1u);
+    s_last = (prev == (unsigned)nblocks - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    double t = 0;
+    for (int i = threadIdx.x; i < nblocks; i += NT) t += __builtin_nontemporal_load(&r.partials[i]);
+    t = block_sum<NT>(t, s_red);
+    if (threadIdx.x == 0) {
+      *r.result = t;
+      *r.counter = 0u;
+    }
+  }
+}
+
+// ----------------------------------------------------------- 3x3 kinematics
+// Compressible neo-Hookean quantities from H = grad u (F = I + H), written
+// without cancellation at small strain:
+//   J - 1 = I1(H) + I2(H) + I3(H),  ln J = log1p(J - 1),
+//   F - F^-T = (H + H^T + H H^T) F^-T.
+template <typename T>
+struct Kin {
+  T G[9];   // F^-1
+  T lnJ;
+  T Jm1;
+};
+
+template <typename T>
+__device__ __forceinline__ T t_log1p(T x);
+template <>
+__device__ __forceinline__ double t_log1p<double>(double x) { return log1p(x); }
+template <>
+__device__ __forceinline__ float t_log1p<float>(float x) { return log1pf(x); }
+
+template <typename T>
+__device__ __forceinline__ bool kinematics(const T H[9], Kin<T> &k) {
+  T I1 = H[0] + H[4] + H[8];
+  T I2 = H[0] * H[4] - H[1] * H[3] + H[0] * H[8] - H[2] * H[6] + H[4] * H[8] - H[5] * H[7];
+  T I3 = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+         H[2] * (H[3] * H[7] - H[4] * H[6]);
+  T Jm1 = I1 + I2 + I3;
+  T J = T(1) + Jm1;
+  k.Jm1 = Jm1;
+  if (!(J > T(0))) return false;
+  k.lnJ = t_log1p<T>(Jm1);
+  T F0 = T(1) + H[0], F4 = T(1) + H[4], F8 = T(1) + H[8];
+  T iJ = T(1) / J;
+  k.G[0] = (F4 * F8 - H[5] * H[7]) * iJ;
+  k.G[1] = (H[2] * H[7] - H[1] * F8) * iJ;
+  k.G[2] = (H[1] * H[5] - H[2] * F4) * iJ;
+  k.G[3] = (H[5] * H[6] - H[3] * F8) * iJ;
+  k.G[4] = (F0 * F8 - H[2] * H[6]) * iJ;
+  k.G[5] = (H[2] * H[3] - F0 * H[5]) * iJ;
+  k.G[6] = (H[3] * H[7] - F4 * H[6]) * iJ;
+  k.G[7] = (H[1] * H[6] - F0 * H[7]) * iJ;
+  k.G[8] = (F0 * F4 - H[1] * H[3]) * iJ;
+  return true;
+}
+
+// First Piola-Kirchhoff stress P = mu (F - F^-T) + lam lnJ F^-T
+//   = [mu (H + H^T + H H^T) + lam lnJ I] F^-T.
+template <typename T>
+__device__ __forceinline__ void first_pk(const T H[9], const Kin<T> &k, T mu, T lam, T Pk[9]) {
+  T Bm[9];
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      T hh = H[i * 3 + 0] * H[j * 3 + 0] + H[i * 3 + 1] * H[j * 3 + 1] + H[i * 3 + 2] * H[j * 3 + 2];
+      Bm[i * 3 + j] = mu * (H[i * 3 + j] + H[j * 3 + i] + hh);
+    }
+  T ll = lam * k.lnJ;
+  Bm[0] += ll; Bm[4] += ll; Bm[8] += ll;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int J = 0; J < 3; J++)
+      Pk[i * 3 + J] = Bm[i * 3 + 0] * k.G[J * 3 + 0] + Bm[i * 3 + 1] * k.G[J * 3 + 1] +
+                      Bm[i * 3 + 2] * k.G[J * 3 + 2];
+}
+
+// Linearised stress dP = mu dF + c1 (G dF G)^T + lam tr(G dF) G^T with
+// G = F^-1 and c1 = mu - lam lnJ (derivative of P along dF).
+template <typename T>
+__device__ __forceinline__ void tangent_dp(const T G[9], T c1, T mu, T lam, const T dF[9],
+                                           T dP[9]) {
+  T A[9];
+#pragma unroll
+  for (int I = 0; I < 3; I++)
+#pragma unroll
+    for (int L = 0; L < 3; L++)
+      A[I * 3 + L] = G[I * 3 + 0] * dF[0 * 3 + L] + G[I * 3 + 1] * dF[1 * 3 + L] +
+                     G[I * 3 + 2] * dF[2 * 3 + L];
+  T trA = lam * (A[0] + A[4] + A[8]);
+#pragma unroll
+  for (int J = 0; J < 3; J++)
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      // (A G)_{J i}
+      T AG = A[J * 3 + 0] * G[0 * 3 + i] + A[J * 3 + 1] * G[1 * 3 + i] + A[J * 3 + 2] * G[2 * 3 + i];
+      dP[i * 3 + J] = mu * dF[i * 3 + J] + c1 * AG + trA * G[J * 3 + i];
+    }
+}
+
+}  // namespace sdme

@@ -1,0 +1,78 @@
+// Host-side launch wrappers shared between the kernel and API translation
+// units of libsdme (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sdme_device.h"
+
+namespace sdme {
+
+// ------------------------------------------------------------ element kernels
+template <typename T>
+int launch_force(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *u, T *R,
+                 T *state, int mask, hipStream_t st);
+template <typename T>
+int launch_tangent(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
+                   const T *state, T msr, const T *v, T *y, int mask, Reduce red, int do_red,
+                   const int *skip, hipStream_t st);
+template <typename T>
+int launch_mass(int P, const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red,
+                int do_red, const int *skip, hipStream_t st);
+template <typename T>
+int launch_diag(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *state,
+                T msr, T *d, int mask, hipStream_t st);
+int launch_energy(int P, const MeshK<double> &m, const double *mu, const double *lam,
+                  const double *u, Reduce red, hipStream_t st);
+int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double *w, double scale,
+                   double *gm, double *gl, hipStream_t st);
+int elem_blocks(int P, int word, int E);
+
+// ------------------------------------------------------------- face kernels
+// mode 0: traction f += scale * int N t dA on face `face`
+// mode 1: penalty force from u (plane z0) on face z=0, energy into red
+// mode 2: penalty stiffness apply y_z += eps int N N x_z dA (all points active)
+int launch_face(int P, const MeshK<double> &m, int mode, int face, const double *t3, double scale,
+                double eps, double z0, double origin_z, const double *u, double *f, Reduce red,
+                int do_red, hipStream_t st);
+int face_blocks(const MeshK<double> &m, int face);
+
+// ------------------------------------------------------------ vector kernels
+// PCG scalars living in device memory (all double).
+struct PcgDev {
+  double rz, pAp, rznew, rr, tol2, bb, alpha, beta;
+  int done;  // 0 running, 1 converged, 2 breakdown, 3 non-finite, 4 iteration limit
+  int iters;
+  int maxit;
+  int pad;
+};
+
+constexpr int VEC_BLOCKS = 1024;
+constexpr int VEC_THREADS = 256;
+
+template <typename T>
+int launch_fill(T *x, T val, int64_t n, hipStream_t st);
+template <typename Td, typename Ts>
+int launch_convert(Td *dst, const Ts *src, double scale, int64_t n, hipStream_t st);
+int launch_axpby(double *y, double alpha, const double *x, double beta, int64_t n, hipStream_t st);
+// y = alpha * x + beta * y + gamma * z
+int launch_axpbypcz(double *y, double alpha, const double *x, double beta, double gamma,
+                    const double *z, int64_t n, hipStream_t st);
+// zero constrained entries (mode 0) or set them to one (mode 1)
+template <typename T>
+int launch_bc(T *x, int mode, const MeshK<T> &m, hipStream_t st);
+// res[0] = sum x*y, res[1] = sum y*y (double accumulation)
+template <typename T>
+int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st);
+// x += scale * double(e)
+int launch_add_scaled_f(double *x, const float *e, double scale, int64_t n, hipStream_t st);
+
+template <typename T>
+int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, int64_t n,
+                    Reduce red2, hipStream_t st);
+template <typename T>
+int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int64_t n,
+                      Reduce red2, hipStream_t st);
+template <typename T>
+int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n, hipStream_t st);
+
+}  // namespace sdme

@@ -1,0 +1,367 @@
+// Vector, reduction and face kernels of libsdme: fused PCG updates with
+// deterministic FP64 reductions (wave shuffles, one partial per block, the
+// last block sums the partials in block order), conversions, Dirichlet
+// masking, and the surface terms (dead traction, rigid-plane penalty).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sdme_device.h"
+#include "sdme_launch.h"
+
+namespace sdme {
+
+constexpr int NTV = VEC_THREADS;
+
+// Two-value deterministic grid reduction.  red.partials holds 2 * gridDim.x
+// doubles; the last block writes res[0], res[1] and returns true in all of
+// its threads.
+__device__ __forceinline__ bool grid_reduce2(double a, double b, Reduce red, double *s_red) {
+  __shared__ bool s_last;
+  double ta = block_sum<NTV>(a, s_red);
+  double tb = block_sum<NTV>(b, s_red);
+  if (threadIdx.x == 0) {
+    red.partials[2 * blockIdx.x] = ta;
+    red.partials[2 * blockIdx.x + 1] = tb;
+    __threadfence();
+    unsigned prev = atomicAdd(red.counter, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  double pa = 0, pb = 0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += NTV) {
+    pa += __builtin_nontemporal_load(&red.partials[2 * i]);
+    pb += __builtin_nontemporal_load(&red.partials[2 * i + 1]);
+  }
+  pa = block_sum<NTV>(pa, s_red);
+  pb = block_sum<NTV>(pb, s_red);
+  if (threadIdx.x == 0) {
+    red.result[0] = pa;
+    red.result[1] = pb;
+    *red.counter = 0u;
+  }
+  return true;
+}
+
+static int grid_for(int64_t n) {
+  int64_t b = (n + NTV - 1) / NTV;
+  return (int)(b < VEC_BLOCKS ? (b > 0 ? b : 1) : VEC_BLOCKS);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_fill(T *x, T val, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) x[i] = val;
+}
+template <typename T>
+int launch_fill(T *x, T val, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(NTV), 0, st, x, val, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename Td, typename Ts>
+__global__ __launch_bounds__(NTV) void k_convert(Td *dst, const Ts *src, double scale, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+    dst[i] = (Td)((double)src[i] * scale);
+}
+template <typename Td, typename Ts>
+int launch_convert(Td *dst, const Ts *src, double scale, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_convert<Td, Ts>), dim3(grid_for(n)), dim3(NTV), 0, st, dst, src, scale, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ __launch_bounds__(NTV) void k_axpbypcz(double *y, double alpha, const double *x,
+                                                  double beta, double gamma, const double *z,
+                                                  int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+    double v = alpha * x[i];
+    if (beta != 0.0) v += beta * y[i];
+    if (z) v += gamma * z[i];
+    y[i] = v;
+  }
+}
+int launch_axpby(double *y, double alpha, const double *x, double beta, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(n)), dim3(NTV), 0, st, y, alpha, x, beta, 0.0,
+                     (const double *)nullptr, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_axpbypcz(double *y, double alpha, const double *x, double beta, double gamma,
+                    const double *z, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(n)), dim3(NTV), 0, st, y, alpha, x, beta, gamma, z, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ __launch_bounds__(NTV) void k_add_scaled_f(double *x, const float *e, double scale,
+                                                      int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+    x[i] += scale * (double)e[i];
+}
+int launch_add_scaled_f(double *x, const float *e, double scale, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_scaled_f, dim3(grid_for(n)), dim3(NTV), 0, st, x, e, scale, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_bc(T *x, int mode, MeshK<T> m) {
+  int64_t n = 3 * (int64_t)m.Nn;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+    int comp = (int)(i / m.Nn);
+    int64_t g = i - (int64_t)comp * m.Nn;
+    int ix = (int)(g % m.Nx), iy = (int)((g / m.Nx) % m.Ny), iz = (int)(g / ((int64_t)m.Nx * m.Ny));
+    if (is_constrained(m.bc, comp, ix, iy, iz, m.Nx, m.Ny, m.Nz)) x[i] = mode ? T(1) : T(0);
+  }
+}
+template <typename T>
+int launch_bc(T *x, int mode, const MeshK<T> &m, hipStream_t st) {
+  hipLaunchKernelGGL(k_bc<T>, dim3(grid_for(3 * (int64_t)m.Nn)), dim3(NTV), 0, st, x, mode, m);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_dot2(const T *x, const T *y, int64_t n, Reduce red) {
+  __shared__ double s_red[NTV / 64];
+  double a = 0, b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+    double xv = (double)x[i], yv = (double)y[i];
+    a += xv * yv;
+    b += yv * yv;
+  }
+  grid_reduce2(a, b, red, s_red);
+}
+template <typename T>
+int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot2<T>, dim3(grid_for(n)), dim3(NTV), 0, st, x, y, n, red2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------- PCG
+// init: p = r / d; rz = r.z; rr = r.r; tol2 = rtol^2 rr (r = b at x = 0).
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, PcgDev *s,
+                                                  double rtol, int maxit, int64_t n, Reduce red) {
+  __shared__ double s_red[NTV / 64];
+  double a = 0, b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+    T z = r[i] / d[i];
+    p[i] = z;
+    a += (double)r[i] * (double)z;
+    b += (double)r[i] * (double)r[i];
+  }
+  if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
+    s->rz = red.result[0];
+    s->rr = red.result[1];
+    s->bb = red.result[1];
+    s->tol2 = rtol * rtol * red.result[1];
+    s->iters = 0;
+    s->maxit = maxit;
+    s->pAp = 0;
+    s->done = (s->rr <= s->tol2) ? 1 : (std::isfinite(s->rr) ? 0 : 3);
+  }
+}
+template <typename T>
+int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, int64_t n,
+                    Reduce red2, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(grid_for(n)), dim3(NTV), 0, st, r, d, p, s, rtol, maxit, n, red2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// update: alpha = rz / pAp; x += alpha p; r -= alpha Ap; Ap = 0;
+// rznew = r.(r/d); rr = r.r; then beta = rznew / rz, convergence test.
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d,
+                                                    PcgDev *s, int64_t n, Reduce red) {
+  __shared__ double s_red[NTV / 64];
+  if (s->done) return;
+  double pAp = s->pAp;
+  double alpha_d = (pAp > 0.0) ? s->rz / pAp : 0.0;
+  T alpha = (T)alpha_d;
+  double a = 0, b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+    T pi = p[i], api = Ap[i];
+    x[i] += alpha * pi;
+    T ri = r[i] - alpha * api;
+    r[i] = ri;
+    Ap[i] = T(0);
+    T z = ri / d[i];
+    a += (double)ri * (double)z;
+    b += (double)ri * (double)ri;
+  }
+  if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
+    double rznew = red.result[0], rr = red.result[1];
+    s->alpha = alpha_d;
+    s->beta = rznew / s->rz;
+    s->rz = rznew;
+    s->rr = rr;
+    s->iters += 1;
+    if (!(pAp > 0.0)) s->done = std::isfinite(pAp) ? 2 : 3;
+    else if (!std::isfinite(rr)) s->done = 3;
+    else if (rr <= s->tol2) s->done = 1;
+    else if (s->iters >= s->maxit) s->done = 4;
+  }
+}
+template <typename T>
+int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int64_t n,
+                      Reduce red2, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(grid_for(n)), dim3(NTV), 0, st, x, r, p, Ap, d, s, n, red2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_pcg_pupdate(T *p, const T *r, const T *d,
+                                                     const PcgDev *s, int64_t n) {
+  if (s->done) return;
+  T beta = (T)s->beta;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+    p[i] = r[i] / d[i] + beta * p[i];
+}
+template <typename T>
+int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_pupdate<T>, dim3(grid_for(n)), dim3(NTV), 0, st, p, r, d, s, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// -------------------------------------------------------------- face terms
+// One block per boundary-face element; nq = P+1 Gauss points per direction
+// (table Bf[nq][n], weights Wf[nq] in the mesh tables).
+template <int P>
+__global__ __launch_bounds__(128) void k_face(MeshK<double> m, int mode, int face, double t0,
+                                              double t1, double t2, double scale, double eps,
+                                              double z0, double origin_z, const double *u,
+                                              double *f, Reduce red, int do_red) {
+  constexpr int n = P + 1, nq = P + 1;
+  using Dm = Dims<P, P + 2, 8>;
+  __shared__ double s_val[nq * nq];
+  __shared__ double s_red[2];
+  const double *Bf = m.tab + Dm::TBF, *Wf = m.tab + Dm::TWF;
+  int dir = face / 2, side = face % 2;
+  int t1d = dir == 0 ? 1 : 0, t2d = dir == 2 ? 1 : 2;
+  int ne[3] = {m.nx, m.ny, m.nz};
+  int fe = blockIdx.x;  // index over face elements: (j * ne[t1d] + i)
+  int ei[3];
+  ei[t1d] = fe % ne[t1d];
+  ei[t2d] = fe / ne[t1d];
+  ei[dir] = side ? ne[dir] - 1 : 0;
+  int Nd[3] = {m.Nx, m.Ny, m.Nz};
+  double hh[3] = {2.0 / m.ih[0], 2.0 / m.ih[1], 2.0 / m.ih[2]};
+  double dA = hh[t1d] * hh[t2d] / 4.0;
+  int local_d = side ? P : 0;
+  double energy = 0;
+  // point values (mode 1: gap pressure; mode 2: x_z at the point)
+  for (int pidx = threadIdx.x; pidx < nq * nq; pidx += blockDim.x) {
+    int i = pidx % nq, j = pidx / nq;
+    double val = 0;
+    if (mode != 0) {
+      for (int b = 0; b < n; b++)
+        for (int a = 0; a < n; a++) {
+          int li[3];
+          li[t1d] = a; li[t2d] = b; li[dir] = local_d;
+          int gi[3] = {ei[0] * P + li[0], ei[1] * P + li[1], ei[2] * P + li[2]};
+          size_t g = ((size_t)gi[2] * Nd[1] + gi[1]) * Nd[0] + gi[0];
+          val += Bf[i * n + a] * Bf[j * n + b] * u[2 * (size_t)m.Nn + g];
+        }
+      if (mode == 1) {
+        double gap = origin_z + val - z0;
+        double w = Wf[i] * Wf[j] * dA;
+        if (gap < 0) energy += 0.5 * eps * gap * gap * w;
+        val = gap < 0 ? eps * (-gap) : 0.0;
+      } else {
+        val = eps * val;
+      }
+    }
+    s_val[pidx] = val;
+  }
+  __syncthreads();
+  for (int midx = threadIdx.x; midx < n * n; midx += blockDim.x) {
+    int a = midx % n, b = midx / n;
+    double acc[3] = {0, 0, 0};
+    for (int j = 0; j < nq; j++)
+      for (int i = 0; i < nq; i++) {
+        double wN = Wf[i] * Wf[j] * dA * Bf[i * n + a] * Bf[j * n + b];
+        if (mode == 0) {
+          acc[0] += wN * t0; acc[1] += wN * t1; acc[2] += wN * t2;
+        } else {
+          acc[2] += wN * s_val[j * nq + i];
+        }
+      }
+    int li[3];
+    li[t1d] = a; li[t2d] = b; li[dir] = local_d;
+    int gi[3] = {ei[0] * P + li[0], ei[1] * P + li[1], ei[2] * P + li[2]};
+    size_t g = ((size_t)gi[2] * Nd[1] + gi[1]) * Nd[0] + gi[0];
+    for (int c = (mode == 0 ? 0 : 2); c < 3; c++)
+      if (acc[c] != 0.0) atomicAdd(&f[c * (size_t)m.Nn + g], scale * acc[c]);
+  }
+  if (do_red) {
+    // block energy -> partial; last block sums (deterministic)
+    double e = energy;
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_down(e, off, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    __shared__ bool s_last;
+    if (threadIdx.x == 0) {
+      red.partials[blockIdx.x] = s_red[0] + s_red[1];
+      __threadfence();
+      s_last = atomicAdd(red.counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+      __threadfence();
+      double t = 0;
+      for (int i = 0; i < (int)gridDim.x; i++) t += __builtin_nontemporal_load(&red.partials[i]);
+      *red.result = t;
+      *red.counter = 0u;
+    }
+  }
+}
+
+int face_blocks(const MeshK<double> &m, int face) {
+  int dir = face / 2;
+  int ne[3] = {m.nx, m.ny, m.nz};
+  int t1d = dir == 0 ? 1 : 0, t2d = dir == 2 ? 1 : 2;
+  return ne[t1d] * ne[t2d];
+}
+
+int launch_face(int P, const MeshK<double> &m, int mode, int face, const double *t3, double scale,
+                double eps, double z0, double origin_z, const double *u, double *f, Reduce red,
+                int do_red, hipStream_t st) {
+  dim3 grid(face_blocks(m, face)), block(128);
+  double t0 = t3 ? t3[0] : 0, t1 = t3 ? t3[1] : 0, t2 = t3 ? t3[2] : 0;
+#define FC(p)                                                                                     \
+  case p:                                                                                         \
+    hipLaunchKernelGGL(k_face<p>, grid, block, 0, st, m, mode, face, t0, t1, t2, scale, eps, z0, \
+                       origin_z, u, f, red, do_red);                                              \
+    break;
+  switch (P) {
+    FC(1) FC(2) FC(3) FC(4) FC(5) FC(6) FC(7) FC(8)
+    default: return -2;
+  }
+#undef FC
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------ instantiations
+template int launch_fill<double>(double *, double, int64_t, hipStream_t);
+template int launch_fill<float>(float *, float, int64_t, hipStream_t);
+template int launch_fill<int>(int *, int, int64_t, hipStream_t);
+template int launch_convert<float, double>(float *, const double *, double, int64_t, hipStream_t);
+template int launch_convert<double, float>(double *, const float *, double, int64_t, hipStream_t);
+template int launch_convert<double, double>(double *, const double *, double, int64_t, hipStream_t);
+template int launch_convert<float, float>(float *, const float *, double, int64_t, hipStream_t);
+template int launch_bc<double>(double *, int, const MeshK<double> &, hipStream_t);
+template int launch_bc<float>(float *, int, const MeshK<float> &, hipStream_t);
+template int launch_dot2<double>(const double *, const double *, int64_t, Reduce, hipStream_t);
+template int launch_dot2<float>(const float *, const float *, int64_t, Reduce, hipStream_t);
+template int launch_pcg_init<double>(const double *, const double *, double *, PcgDev *, double,
+                                     int, int64_t, Reduce, hipStream_t);
+template int launch_pcg_init<float>(const float *, const float *, float *, PcgDev *, double, int,
+                                    int64_t, Reduce, hipStream_t);
+template int launch_pcg_update<double>(double *, double *, const double *, double *,
+                                       const double *, PcgDev *, int64_t, Reduce, hipStream_t);
+template int launch_pcg_update<float>(float *, float *, const float *, float *, const float *,
+                                      PcgDev *, int64_t, Reduce, hipStream_t);
+template int launch_pcg_pupdate<double>(double *, const double *, const double *, const PcgDev *,
+                                        int64_t, hipStream_t);
+template int launch_pcg_pupdate<float>(float *, const float *, const float *, const PcgDev *,
+                                       int64_t, hipStream_t);
+
+}  // namespace sdme

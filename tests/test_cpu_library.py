@@ -1,0 +1,81 @@
+"""CPU checks of libsdme: the shared library loads and exports every entry
+point declared in include/sdme.h; the host-side basis construction, gather
+map, Dirichlet flags and affine-field expansion match the oracle; argument
+validation rejects bad input before any device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis as ob
+from oracle import solvers as osv
+from paper_2104_13466_amd import inputs, sdme
+from tests.oracle_setup import make
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sdme.h")
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    text = open(HEADER).read()
+    declared = sorted(set(re.findall(r"\b(sdme_[a-z_0-9]+)\s*\(", text)))
+    assert len(declared) >= 25
+    L = ctypes.CDLL(sdme.lib_path())
+    missing = [d for d in declared if not hasattr(L, d)]
+    assert not missing, missing
+    # the binding covers every declared symbol
+    assert set(declared) <= set(sdme.SIGNATURES), set(declared) - set(sdme.SIGNATURES)
+
+
+@pytest.mark.parametrize("kind", [ob.NODAL, ob.MODAL, ob.SDME_M, ob.SDME_K, ob.SDME_H])
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5, 6, 8, 10])
+def test_basis_matches_oracle(kind, P):
+    Q = P + 2
+    t = sdme.basis_build(P, Q, kind, 0.5, 100.0)
+    b, x, w, B, D = ob.build(P, Q, kind)
+    assert np.abs(t["x"] - x).max() < 1e-15
+    assert np.abs(t["w"] - w).max() < 1e-14
+    assert np.abs(t["B"] - B).max() < 1e-12
+    assert np.abs(t["D"] - D).max() < 1e-11 * max(1.0, np.abs(D).max())
+    assert np.abs(t["M1"] - b.M1).max() < 1e-13
+    assert np.abs(t["K1"] - b.K1).max() < 1e-11 * max(1.0, np.abs(b.K1).max())
+    if kind >= ob.SDME_M and P >= 2:
+        assert np.allclose(t["lambda_s"], b.lambda_s, rtol=1e-12)
+
+
+def test_basis_eval_matches_oracle():
+    pts = np.linspace(-1, 1, 23)
+    V, dV = sdme.basis_eval(6, ob.SDME_H, pts)
+    b = ob.Basis1D(6, ob.SDME_H)
+    Vr, dVr = b.eval(pts)
+    assert np.abs(V - Vr).max() < 1e-12 and np.abs(dV - dVr).max() < 1e-10
+
+
+@pytest.mark.parametrize("n,P,bits", [((3, 2, 2), 3, inputs.face_bits(0)),
+                                      ((2, 3, 1), 4, inputs.face_bits(4) | inputs.face_bits(5)),
+                                      ((1, 1, 2), 2, (1 << 18) - 1)])
+def test_host_maps_match_oracle(n, P, bits):
+    ctx = sdme.Context(n, (1.0, 2.0, 0.5), P, basis=ob.SDME_H, dirichlet=bits)
+    pb, basis = make(n, (1.0, 2.0, 0.5), P, dirichlet=bits)
+    assert np.array_equal(ctx.gather_indices(), pb.mesh.gather_map())
+    assert np.array_equal(ctx.dirichlet_flags(), (pb.mask == 0).astype(np.uint8))
+    G = np.array([[0.1, 0.2, -0.3], [0.05, -0.2, 0.0], [0.3, 0.1, -0.2]])
+    a = ctx.affine_field([0.5, -1.0, 2.0], G)
+    ref = osv.affine_field(pb.mesh, basis, (0, 0, 0), [0.5, -1.0, 2.0], G)
+    assert np.abs(a - ref).max() < 1e-12
+    ctx.close()
+
+
+def test_argument_validation():
+    with pytest.raises(sdme.SdmeError) as e:
+        sdme.basis_build(0, 2, ob.SDME_H)
+    assert e.value.code == -1
+    with pytest.raises(sdme.SdmeError):
+        sdme.basis_build(4, 4, ob.SDME_H)  # Q < P+1
+    with pytest.raises(sdme.SdmeError):
+        sdme.Context((2, 2, 2), (1, 1, 1), 9)  # order beyond the compiled kernels
+    with pytest.raises(sdme.SdmeError):
+        sdme.Context((0, 2, 2), (1, 1, 1), 3)
+    with pytest.raises(sdme.SdmeError):
+        sdme.Context((2, 2, 2), (1, 1, 1), 3, Q=4)  # only Q = P+2 is compiled
