@@ -1,0 +1,285 @@
+"""Benchmark of the libsdme hot path on one MI355X.
+
+Workload (default): compress_p4 -- unit cube of 47^3 hexahedra, P = 4,
+Q = 6 Gauss points per direction, SDME-H basis (k = 0.5, lambda = 100),
+compressible neo-Hookean E = 1e3, nu = 0.3; z = 0 clamped, z = 1 moved by
+(0, 0, -0.2) (20 % compression); 6,751,269 slots, 20,253,807 DOFs.  Initial
+guess: the affine 20 % compression plus a seeded U(-a, a) perturbation of
+every free coefficient, a = 1e-3 h (h the element edge) (synthetic input; the paper's meshes are not
+available).
+
+One step = one Newton-Raphson iteration of the hot path from that fixed
+initial state: internal force R(u) with the linearisation state, the Jacobi
+diagonal, the Jacobi-PCG solve of K_T du = -R to 1e-8 relative residual in
+mixed precision (FP32 inner PCG with FP32 state/operator/vectors and FP64
+dots, FP64 defect correction), and the update u += du.  value = tangent
+applies x DOFs / step time (GDOF/s, whole step).  Besides the timed steps the
+same Newton iteration runs once with FP64 PCG (newton_iteration: mixed vs
+FP64), --solve adds the load-stepped Newton-PCG solve to 1e-8 in both
+precisions (newton_pcg), the oracle is timed on a bounded sample of the same workload on
+the host (cpu_baseline), and the dominant kernel (FP32 stored-state tangent
+action in the inner PCG) is timed per launch by HIP events on its stream.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve]
+       [--no-cpu-baseline] [--kernel-table]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tangent-apply GDOF/s; Newton-PCG solve to 1e-8, mixed-FP32 vs FP64"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK = 157.3   # TFLOP/s (datasheet, dense)
+FP64_PEAK = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(name):
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.sdme import Context
+    w = inputs.WORKLOADS[name]
+    n, L, P = w["n"], w["L"], w["P"]
+    ctx = Context(n, L, P, basis=w["kind"], dirichlet=w["dirichlet"])
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    dev = torch.device("cuda")
+    mu = torch.full((ctx.E,), mu0, dtype=torch.float64, device=dev)
+    lam = torch.full((ctx.E,), lam0, dtype=torch.float64, device=dev)
+    mat = Context.material(mu, lam, w["rho"])
+    G = np.zeros((3, 3))
+    G[2, 2] = -0.2
+    free = 1.0 - ctx.dirichlet_flags().astype(np.float64)
+    amp = 1e-3 * min(L[i] / n[i] for i in range(3))
+    u0 = ctx.affine_field([0, 0, 0], G) + free * inputs.random_coeffs(w["seed"], n, P, amp)
+    u0 = torch.tensor(u0, device=dev)
+    return w, ctx, mat, u0
+
+
+def newton_iteration(ctx, mat, prec, u, R, du, rtol):
+    """R(u) (masked) -> psi = -R -> PCG (K_T(u) du = psi) -> u += du."""
+    from paper_2104_13466_amd.sdme import FP64, MASK_BC
+    ctx.internal_force(mat, FP64, u, R, flags=MASK_BC)
+    ctx.axpby(-1.0, R, 0.0, R)
+    st = ctx.jacobi_pcg(mat, prec, R, du, u_lin=u, rtol=rtol)
+    ctx.axpby(1.0, du, 1.0, u)
+    return st
+
+
+def kernel_table(ctx, mat, u0):
+    """Per-launch times of the element operators at the workload (HIP events)."""
+    import torch
+
+    from paper_2104_13466_amd.sdme import FP32, FP64
+    N = 3 * ctx.Nn
+    rows = []
+    for prec, dt in ((FP64, torch.float64), (FP32, torch.float32)):
+        u = u0.to(dt)
+        v = torch.rand(N, dtype=dt, device="cuda")
+        y = torch.zeros_like(v)
+        st = torch.empty(ctx.nqp * 10, dtype=dt, device="cuda")
+        ctx.linearize(mat, prec, u, st)
+        cases = [
+            ("tangent_state", lambda: ctx.tangent_apply(mat, prec, v, y, state=st)),
+            ("tangent_recompute", lambda: ctx.tangent_apply(mat, prec, v, y, u_lin=u)),
+            ("internal_force", lambda: ctx.internal_force(mat, prec, u, y)),
+            ("force_and_state", lambda: ctx.internal_force(mat, prec, u, y, state=st)),
+            ("mass", lambda: ctx.mass_apply(1.0, prec, v, y)),
+            ("jacobi_diag", lambda: ctx.jacobi_diag(mat, prec, st, 0.0, y)),
+        ]
+        for name, fn in cases:
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rows.append(("fp64" if prec == FP64 else "fp32", name, ms, N / ms / 1e6))
+            log("kernel %-4s %-18s %8.3f ms/call  %7.2f GDOF/s (incl. output fill)" % rows[-1])
+    return rows
+
+
+def cpu_baseline(w, seconds=10.0):
+    """The oracle's direct tangent action timed on the host on a sub-box of the
+    workload mesh (same P, Q, basis, element size)."""
+    from oracle import basis as ob
+    from oracle import fem
+    from paper_2104_13466_amd import inputs
+    P, Q = w["P"], w["P"] + 2
+    n = w["n"]
+    sub = (min(24, n[0]), min(24, n[1]), min(24, n[2]))
+    h = [w["L"][i] / n[i] for i in range(3)]
+    b, x, wq, B, D = ob.build(P, Q, w["kind"])
+    mesh = fem.Mesh(sub[0], sub[1], sub[2], P, Q, h, B, D, wq)
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    mu = np.full(mesh.E, mu0)
+    lam = np.full(mesh.E, lam0)
+    u = inputs.random_coeffs(w["seed"], sub, P, 1e-3)
+    v = inputs.uniform(w["seed"], u.size, -1, 1, stream=3)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        mesh.tangent_apply(mu, lam, u, v)
+        k += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": k * 3 * mesh.Nn / t / 1e9, "unit": "GDOF/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d x tangent action on a %dx%dx%d-element sub-box (P=%d, %d DOF) of the "
+                      "workload mesh, %.1f s" % (k, sub[0], sub[1], sub[2], P, 3 * mesh.Nn, t)}
+
+
+def full_solve(ctx, mat, u0, a):
+    """Newton-PCG time-to-solution in FP64 and mixed: the top displacement is
+    applied in equal increments (load stepping); each increment starts from the
+    previous solution plus the affine increment and runs the damped Newton of
+    sdme_newton_static to 1e-8 with PCG to 1e-8."""
+    import torch
+
+    from paper_2104_13466_amd.sdme import FP32, FP64
+    G = np.zeros((3, 3))
+    G[2, 2] = -0.2 / a.increments
+    inc = torch.tensor(ctx.affine_field([0, 0, 0], G), device="cuda")
+    out = {}
+    sols = {}
+    for prec, name in ((FP64, "fp64"), (FP32, "mixed")):
+        u = torch.zeros_like(u0)
+        tot = {"newton": 0, "pcg_iterations": 0, "outer": 0}
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(a.increments):
+            ctx.axpby(1.0, inc, 1.0, u)
+            st = ctx.newton_static(mat, prec, u, newton_rtol=a.rtol, pcg_rtol=a.rtol)
+            for key in tot:
+                tot[key] += st["iterations" if key == "pcg_iterations" else key]
+            log("solve %s increment %d: %s" % (name, k, st))
+        torch.cuda.synchronize()
+        tot["seconds"] = round(time.perf_counter() - ts, 3)
+        out[name] = tot
+        sols[name] = u
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    out["max_rel_diff_mixed_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
+                                         sols["fp64"].abs().max()).item()
+    out["increments"] = a.increments
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="compress_p4")
+    ap.add_argument("--solve", action="store_true")
+    ap.add_argument("--increments", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-table", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path (slab partition + halo "
+              "exchange over RCCL) is not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2104_13466_amd.sdme import FP32, FP64
+
+    log("setup %s" % a.workload)
+    w, ctx, mat, u0 = setup(a.workload)
+    N = 3 * ctx.Nn
+    log("mesh %s P=%d: %d DOF, %d elements, %d Gauss points" % (w["n"], w["P"], N, ctx.E, ctx.nqp))
+    if a.kernel_table:
+        kernel_table(ctx, mat, u0)
+    u = u0.clone()
+    R = torch.zeros(N, dtype=torch.float64, device="cuda")
+    du = torch.zeros_like(R)
+    # warmup
+    for i in range(a.warmup):
+        u.copy_(u0)
+        st = newton_iteration(ctx, mat, FP32, u, R, du, a.rtol)
+        log("warmup %d: pcg its %d outer %d rel %.2e (%.0f ms)" % (i, st["iterations"], st["outer"],
+                                                                 st["rel_residual"], st["time_ms"]))
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    applies = 0
+    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        ts = time.perf_counter()
+        u.copy_(u0)
+        st = newton_iteration(ctx, mat, FP32, u, R, du, a.rtol)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        applies += st["iterations"] + st["outer"]
+        log("step %d: pcg its %d outer %d rel %.2e %.1f ms" % (i, st["iterations"], st["outer"],
+                                                             st["rel_residual"], 1e3 * times[-1]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile(False)
+    ms_step = 1e3 * elapsed / a.steps
+    value = applies * N / elapsed / 1e9
+    # dominant kernel: FP32 stored-state tangent action inside the inner PCG
+    k_ms = prof["fp32_ms"] / max(prof["fp32_count"], 1)
+    bytes_launch = 40 * ctx.nqp + 8 * N  # state (10 x fp32 per Gauss point) + read v + write y
+    achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%dx%d hexahedra, P=%d, Q=%d, SDME-H, %d DOF, 20%% "
+                               "compression, Newton iteration with mixed FP32/FP64 Jacobi-PCG to "
+                               "%.0e" % (a.workload, w["n"][0], w["n"][1], w["n"][2], w["P"],
+                                         w["P"] + 2, N, a.rtol),
+                   "dofs": N, "elements": ctx.E, "gauss_points": ctx.nqp},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_tangent<4,6,float,state> (FP32 stored-state tangent action)",
+                     "avg_launch_ms": round(k_ms, 4), "launches": prof["fp32_count"],
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel_gdofs": round(N / (k_ms * 1e-3) / 1e9, 2)},
+        "tangent_applies_per_step": applies / a.steps,
+    }
+    # FP64 PCG vs mixed on the same Newton iteration (same state, same tolerance)
+    uf = u0.clone()
+    duf = torch.zeros_like(R)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    stf = newton_iteration(ctx, mat, FP64, uf, R, duf, a.rtol)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - ts
+    dd = ((uf - u).abs().max() / (uf - u0).abs().max()).item()
+    log("fp64 newton iteration: pcg its %d, %.1f ms" % (stf["iterations"], 1e3 * t64))
+    result["newton_iteration"] = {
+        "fp64": {"ms": round(1e3 * t64, 1), "pcg_iterations": stf["iterations"]},
+        "mixed": {"ms": round(ms_step, 1), "pcg_iterations": applies / a.steps},
+        "speedup_mixed_vs_fp64": round(1e3 * t64 / ms_step, 3),
+        "max_rel_diff_increment_mixed_vs_fp64": dd}
+    if a.solve:
+        result["newton_pcg"] = full_solve(ctx, mat, u0, a)
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

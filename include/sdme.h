@@ -246,9 +246,13 @@ int sdme_workspace_bytes(const sdme_ctx *ctx, int op, int prec, size_t *bytes);
  * (x overwritten, zero on constrained DOFs; b masked internally).  Stops when
  * ||b - A x||_2 <= rtol ||b||_2.
  * prec = SDME_FP64: FP64 vectors, state and operator.
- * prec = SDME_FP32: mixed precision -- FP32 inner PCG (FP32 state, operator
- * and vectors, FP64 dots) to inner_rtol, FP64 defect correction r = b - A x
- * with the FP64 operator until rtol.
+ * prec = SDME_FP32: mixed precision -- the CG iteration runs in FP32 (FP32
+ * state, operator and vectors, FP64 dots) while the solution is accumulated
+ * in FP64; each time the FP32 residual has dropped by the factor inner_rtol
+ * (and when it reaches rtol) it is replaced by the FP64 defect
+ * r = b - A x computed with the FP64 operator, keeping the search direction
+ * (residual replacement / reliable updates).  The stop test uses the FP64
+ * defect.  stats->outer counts the replacements; the drivers use 1e-2.
  * mass_only != 0 solves with the mass matrix alone (K_T omitted, u_lin unused).
  * Synchronises.  Errors: SDME_ENOCONV (maxit), SDME_EBREAKDOWN, SDME_EJAC,
  * SDME_ENOMEM (ws_bytes too small).
@@ -328,6 +332,15 @@ int sdme_explicit_adjoint_step(sdme_ctx *ctx, const sdme_material *mat, const do
                                double dt, int first, double mass_rtol, double *g_mu,
                                double *g_lam, sdme_stats *stats, void *ws, size_t ws_bytes,
                                void *stream);
+
+/* Per-launch timing of the PCG operator (the tangent or mass action inside
+ * sdme_jacobi_pcg and the drivers), by HIP events recorded on the solve stream
+ * around each operator launch that runs.  Returns in ms_out/count_out the
+ * totals accumulated since the previous call ([0] FP64 operator, [1] FP32
+ * operator; either may be NULL), then resets them and switches recording on
+ * (enable != 0) or off.  Host-only bookkeeping; events are created on first
+ * enable. */
+int sdme_profile(sdme_ctx *ctx, int enable, double ms_out[2], int64_t count_out[2]);
 
 /* lam_out = mask (u - target); *J_host = 1/2 ||lam_out||^2 (synchronises). */
 int sdme_misfit(sdme_ctx *ctx, const double *u, const double *target, double *lam_out,

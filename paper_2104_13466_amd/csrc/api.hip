@@ -37,6 +37,12 @@ struct sdme_ctx {
   MeshK<float> m32;
   int device = 0;
   bool dev_ready = false;
+  // optional per-launch timing of the PCG operator (HIP events on the solve
+  // stream): [0] FP64 operator, [1] FP32 operator
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  double prof_ms[2] = {0, 0};
+  int64_t prof_count[2] = {0, 0};
   std::vector<double> tab_host;
 };
 
@@ -129,27 +135,91 @@ int apply_op(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *v,
                            st);
 }
 
+// Residual replacement ("reliable updates") of the mixed-precision CG: the
+// FP32 iteration keeps its search direction while the solution is accumulated
+// in FP64 and the FP32 residual is periodically replaced by the true FP64
+// residual b - A64 x64 (defect correction inside one Krylov sequence).
+struct Replace {
+  const Op<double> *op64;
+  double *x64, *r64, *Ap64;
+  const double *bm;
+  double delta;
+  int count;
+};
+
+int do_replace(sdme_ctx *c, const sdme_material *mat, Replace &rep, float *x32, float *r32,
+               const float *d32, float *p32, PcgDev *s, hipStream_t st) {
+  int64_t N = 3 * c->Nn;
+  if (launch_add_scaled_f(rep.x64, x32, 1.0, N, st) || launch_fill<float>(x32, 0.0f, N, st) ||
+      launch_fill<double>(rep.Ap64, 0.0, N, st))
+    return SDME_EDEVICE;
+  Reduce none{c->partials, c->counter, c->results + 8};
+  if (apply_op<double>(c, mat, *rep.op64, rep.x64, rep.Ap64, none, 0, nullptr, st) ||
+      launch_axpbypcz(rep.r64, 1.0, rep.bm, 0.0, -1.0, rep.Ap64, N, st) ||
+      launch_pcg_replace(r32, rep.r64, d32, p32, s, rep.delta, N, red_at(c, 2), st))
+    return SDME_EDEVICE;
+  rep.count++;
+  return SDME_OK;
+}
+
 // Jacobi PCG in precision T on vectors of type T: b masked on input, x out.
+// The operator's p^T A p comes from a separate streaming dot product.
 template <typename T>
 int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b, T *x, const T *d,
              double rtol, int maxit, T *r, T *p, T *Ap, int slot, int *iters, double *rel,
-             hipStream_t st) {
+             hipStream_t st, Replace *rep = nullptr) {
   int64_t N = 3 * c->Nn;
   PcgDev *s = c->pcg + slot;
   if (launch_fill<T>(x, T(0), N, st) || launch_fill<T>(Ap, T(0), N, st) ||
       launch_convert<T, T>(r, b, 1.0, N, st))
     return SDME_EDEVICE;
-  if (launch_pcg_init<T>(r, d, p, s, rtol, maxit, N, red_at(c, 2), st)) return SDME_EDEVICE;
-  Reduce rpap{c->partials, c->counter, &s->pAp};
+  if (launch_pcg_init<T>(r, d, p, s, rtol, maxit, rep ? rep->delta : 0.0, N, red_at(c, 2), st))
+    return SDME_EDEVICE;
+  Reduce none{c->partials, c->counter, c->results + 8};
   for (;;) {
     if (hipMemcpyAsync(c->h_pcg + slot, s, sizeof(PcgDev), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return SDME_EDEVICE;
-    if (c->h_pcg[slot].done) break;
+    int done = c->h_pcg[slot].done;
+    if constexpr (sizeof(T) == 4) {
+      if (rep && (done == 5 || done == 1)) {
+        // the FP32 residual met the replacement or the stop threshold: replace
+        // it by the FP64 defect; stop only if that defect meets the tolerance
+        if (rep->count >= 1000) return SDME_ENOCONV;
+        int rc = do_replace(c, mat, *rep, x, r, d, p, s, st);
+        if (rc) return rc;
+        if (hipMemcpyAsync(c->h_pcg + slot, s, sizeof(PcgDev), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return SDME_EDEVICE;
+        done = c->h_pcg[slot].done;  // 1: FP64 defect converged, 3: non-finite, 0: go on
+      }
+    }
+    if (done) break;
+    int it0 = c->h_pcg[slot].iters;
     for (int j = 0; j < CHUNK; j++) {
-      if (apply_op<T>(c, mat, op, p, Ap, rpap, 1, &s->done, st)) return SDME_EDEVICE;
+      if (c->prof && hipEventRecord(c->ev[2 * j], st) != hipSuccess) return SDME_EDEVICE;
+      if (apply_op<T>(c, mat, op, p, Ap, none, 0, &s->done, st)) return SDME_EDEVICE;
+      if (c->prof && hipEventRecord(c->ev[2 * j + 1], st) != hipSuccess) return SDME_EDEVICE;
+      if (launch_pcg_pap<T>(p, Ap, s, N, red_at(c, 6), st)) return SDME_EDEVICE;
       if (launch_pcg_update<T>(x, r, p, Ap, d, s, N, red_at(c, 4), st)) return SDME_EDEVICE;
       if (launch_pcg_pupdate<T>(p, r, d, s, N, st)) return SDME_EDEVICE;
+    }
+    if (c->prof) {
+      // count only the iterations that ran (later ones return at once)
+      if (hipMemcpyAsync(c->h_pcg + slot, s, sizeof(PcgDev), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return SDME_EDEVICE;
+      int ran = c->h_pcg[slot].iters - it0;
+      int k = sizeof(T) == 8 ? 0 : 1;
+      for (int j = 0; j < ran && j < CHUNK; j++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->ev[2 * j], c->ev[2 * j + 1]) != hipSuccess)
+          return SDME_EDEVICE;
+        c->prof_ms[k] += ms;
+        c->prof_count[k] += 1;
+      }
     }
   }
   const PcgDev &h = c->h_pcg[slot];
@@ -216,47 +286,21 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
     }
     return rc;
   }
-  // mixed: FP32 inner PCG + FP64 defect correction
+  // mixed: FP32 PCG (FP32 state, operator and vectors, FP64 dots) with FP64
+  // residual replacement and FP64 accumulation of the solution
   if (!mass_only && launch_convert<float, double>(w.state32, state64, 1.0, c->nqp * 10, st))
     return SDME_EDEVICE;
-  if (launch_convert<float, double>(w.d32, w.d64, 1.0, N, st)) return SDME_EDEVICE;
-  Op<float> op32{mass_only ? 2 : 0, w.state32, nullptr, (float)(shift * mat->rho), (float)mat->rho};
-  if (launch_fill<double>(x, 0.0, N, st) || launch_convert<double, double>(w.r64, w.bm, 1.0, N, st))
+  if (launch_convert<float, double>(w.d32, w.d64, 1.0, N, st) ||
+      launch_convert<float, double>(w.b32, w.bm, 1.0, N, st) || launch_fill<double>(x, 0.0, N, st))
     return SDME_EDEVICE;
-  double dd[2];
-  int rc = dot2<double>(c, w.bm, w.bm, N, dd, st);
-  if (rc) return rc;
-  double bb = dd[1];
-  int total = 0, outer = 0;
-  rc = SDME_OK;
-  double relres = bb > 0 ? 1.0 : 0.0;
-  while (bb > 0) {
-    rc = dot2<double>(c, w.r64, w.r64, N, dd, st);
-    if (rc) return rc;
-    double rr = dd[1];
-    relres = std::sqrt(rr / bb);
-    if (!std::isfinite(rr)) { rc = SDME_ENAN; break; }
-    if (rr <= rtol * rtol * bb) { rc = SDME_OK; break; }
-    if (total >= maxit || outer >= 200) { rc = SDME_ENOCONV; break; }
-    double nr = std::sqrt(rr);
-    if (launch_convert<float, double>(w.b32, w.r64, 1.0 / nr, N, st)) return SDME_EDEVICE;
-    int its_in = 0;
-    double rel_in = 0;
-    int rci = pcg_core<float>(c, mat, op32, w.b32, w.e32, w.d32, inner_rtol, maxit - total, w.r32,
-                              w.p32, w.Ap32, 1, &its_in, &rel_in, st);
-    total += its_in;
-    outer++;
-    if (launch_add_scaled_f(x, w.e32, nr, N, st)) return SDME_EDEVICE;
-    // r64 = bm - A64 x
-    if (launch_fill<double>(w.Ap64, 0.0, N, st)) return SDME_EDEVICE;
-    if (apply_op<double>(c, mat, op64, x, w.Ap64, red_at(c, 6), 0, nullptr, st)) return SDME_EDEVICE;
-    if (launch_axpbypcz(w.r64, 1.0, w.bm, 0.0, -1.0, w.Ap64, N, st)) return SDME_EDEVICE;
-    if (rci == SDME_EBREAKDOWN || rci == SDME_ENAN) { rc = rci; break; }
-  }
+  Op<float> op32{mass_only ? 2 : 0, w.state32, nullptr, (float)(shift * mat->rho), (float)mat->rho};
+  Replace rep{&op64, x, w.r64, w.Ap64, w.bm, inner_rtol, 0};
+  int rc = pcg_core<float>(c, mat, op32, w.b32, w.e32, w.d32, rtol, maxit, w.r32, w.p32, w.Ap32, 1,
+                           &its, &rel, st, &rep);
   if (stats) {
-    stats->iterations += total;
-    stats->outer += outer;
-    stats->rel_residual = relres;
+    stats->iterations += its;
+    stats->outer += rep.count;
+    stats->rel_residual = rel;
   }
   return rc;
 }
@@ -413,8 +457,30 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   return SDME_OK;
 }
 
+extern "C" int sdme_profile(sdme_ctx *c, int enable, double ms_out[2], int64_t count_out[2]) {
+  if (!c) return SDME_EINVAL;
+  if (ms_out) {
+    ms_out[0] = c->prof_ms[0];
+    ms_out[1] = c->prof_ms[1];
+  }
+  if (count_out) {
+    count_out[0] = c->prof_count[0];
+    count_out[1] = c->prof_count[1];
+  }
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * CHUNK);
+    for (auto &e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) return SDME_EDEVICE;
+  }
+  c->prof = enable != 0;
+  c->prof_ms[0] = c->prof_ms[1] = 0;
+  c->prof_count[0] = c->prof_count[1] = 0;
+  return SDME_OK;
+}
+
 extern "C" int sdme_destroy(sdme_ctx *c) {
   if (!c) return SDME_EINVAL;
+  for (auto &e : c->ev) hipEventDestroy(e);
   if (c->dev_ready) {
     int dev = 0;
     hipGetDevice(&dev);
@@ -763,11 +829,24 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
   double psi0 = -1, nrm = 0;
   int rc = SDME_OK;
   double shift = dyn ? dyn->b1 : 0.0;
+  // Damped Newton: when the updated state inverts an element (det F <= 0),
+  // the last increment is halved (u -= alpha du, alpha halved) up to 20 times.
+  double alpha = 1.0;
+  int halvings = 0;
   for (int k = 0;; k++) {
     if ((rc = clear_flag(c, st))) return rc;
-    if (launch_force<double>(c->P, c->m64, mat->mu, mat->lam, u, R, state64, 1, st))
+    if (launch_fill<double>(R, 0.0, N, st) ||
+        launch_force<double>(c->P, c->m64, mat->mu, mat->lam, u, R, state64, 1, st))
       return SDME_EDEVICE;
-    if ((rc = read_flag(c, st))) return rc;
+    if ((rc = read_flag(c, st))) {
+      if (rc != SDME_EJAC || k == 0 || halvings >= 20) return rc;
+      alpha *= 0.5;
+      halvings++;
+      if (launch_axpby(u, -alpha, du, 1.0, N, st)) return SDME_EDEVICE;
+      k--;
+      continue;
+    }
+    alpha = 1.0;
     // psi = f - R
     if (f_ext) {
       if (launch_axpbypcz(psi, 1.0, f_ext, 0.0, -1.0, R, N, st)) return SDME_EDEVICE;
@@ -794,7 +873,7 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
     if (stats) stats->newton_rel = psi0 > 0 ? nrm / psi0 : 0.0;
     if (nrm <= newton_rtol * psi0 || nrm == 0.0) break;
     if (k >= max_newton) return SDME_ENOCONV;
-    rc = solve_linear(c, mat, prec, state64, shift, false, psi, du, pcg_rtol, max_pcg, 1e-4, w,
+    rc = solve_linear(c, mat, prec, state64, shift, false, psi, du, pcg_rtol, max_pcg, 1e-2, w,
                       stats, st);
     if (rc) return rc;
     if (launch_axpby(u, 1.0, du, 1.0, N, st)) return SDME_EDEVICE;

@@ -40,13 +40,16 @@ int face_blocks(const MeshK<double> &m, int face);
 // PCG scalars living in device memory (all double).
 struct PcgDev {
   double rz, pAp, rznew, rr, tol2, bb, alpha, beta;
-  int done;  // 0 running, 1 converged, 2 breakdown, 3 non-finite, 4 iteration limit
+  double upd2;   // residual-replacement threshold (mixed precision); 0 = off
+  double rz_old; // r.z before the last update (for beta after a replacement)
+  int done;  // 0 running, 1 converged, 2 breakdown, 3 non-finite, 4 iteration limit,
+             // 5 residual replacement requested
   int iters;
   int maxit;
   int pad;
 };
 
-constexpr int VEC_BLOCKS = 1024;
+constexpr int VEC_BLOCKS = 4096;
 constexpr int VEC_THREADS = 256;
 
 template <typename T>
@@ -67,12 +70,19 @@ int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st);
 int launch_add_scaled_f(double *x, const float *e, double scale, int64_t n, hipStream_t st);
 
 template <typename T>
-int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, int64_t n,
-                    Reduce red2, hipStream_t st);
+int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, double delta,
+                    int64_t n, Reduce red2, hipStream_t st);
 template <typename T>
 int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int64_t n,
                       Reduce red2, hipStream_t st);
 template <typename T>
 int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n, hipStream_t st);
+// pAp = p . Ap (skipped when done)
+template <typename T>
+int launch_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n, Reduce red2, hipStream_t st);
+// residual replacement: r32 = float(r64); rz = r32.(r32/d); beta = rz/rz_old;
+// done = (r64.r64 <= tol2); upd2 = delta^2 r64.r64; then p = r32/d + beta p
+int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,
+                       double delta, int64_t n, Reduce red2, hipStream_t st);
 
 }  // namespace sdme

@@ -139,7 +139,8 @@ int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st) 
 // init: p = r / d; rz = r.z; rr = r.r; tol2 = rtol^2 rr (r = b at x = 0).
 template <typename T>
 __global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, PcgDev *s,
-                                                  double rtol, int maxit, int64_t n, Reduce red) {
+                                                  double rtol, int maxit, double delta, int64_t n,
+                                                  Reduce red) {
   __shared__ double s_red[NTV / 64];
   double a = 0, b = 0;
   for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
@@ -153,6 +154,8 @@ __global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, 
     s->rr = red.result[1];
     s->bb = red.result[1];
     s->tol2 = rtol * rtol * red.result[1];
+    s->rz_old = red.result[0];
+    s->upd2 = delta * delta * red.result[1];
     s->iters = 0;
     s->maxit = maxit;
     s->pAp = 0;
@@ -160,9 +163,66 @@ __global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, 
   }
 }
 template <typename T>
-int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, int64_t n,
-                    Reduce red2, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(grid_for(n)), dim3(NTV), 0, st, r, d, p, s, rtol, maxit, n, red2);
+int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, double delta,
+                    int64_t n, Reduce red2, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(grid_for(n)), dim3(NTV), 0, st, r, d, p, s, rtol, maxit,
+                     delta, n, red2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n,
+                                                 Reduce red) {
+  __shared__ double s_red[NTV / 64];
+  if (s->done) return;
+  double a = 0;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+    a += (double)p[i] * (double)Ap[i];
+  if (grid_reduce2(a, 0.0, red, s_red) && threadIdx.x == 0) s->pAp = red.result[0];
+}
+template <typename T>
+int launch_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n, Reduce red2, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_pap<T>, dim3(grid_for(n)), dim3(NTV), 0, st, p, Ap, s, n, red2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Residual replacement of the mixed-precision CG: the recursively updated
+// FP32 residual is replaced by the true FP64 residual b - A x (computed by the
+// caller); the search direction is kept (reliable updates).
+__global__ __launch_bounds__(NTV) void k_pcg_replace(float *r32, const double *r64,
+                                                     const float *d, PcgDev *s, double delta,
+                                                     int64_t n, Reduce red) {
+  __shared__ double s_red[NTV / 64];
+  double a = 0, b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
+    double rv = r64[i];
+    float rf = (float)rv;
+    r32[i] = rf;
+    a += (double)rf * (double)(rf / d[i]);
+    b += rv * rv;
+  }
+  if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
+    double rz = red.result[0], rr = red.result[1];
+    s->beta = rz / s->rz_old;
+    s->rz = rz;
+    s->rr = rr;
+    s->upd2 = delta * delta * rr;
+    s->done = (rr <= s->tol2) ? 1 : (std::isfinite(rr) ? 0 : 3);
+  }
+}
+__global__ __launch_bounds__(NTV) void k_pcg_pupdate_force(float *p, const float *r,
+                                                           const float *d, const PcgDev *s,
+                                                           int64_t n) {
+  if (s->done == 1 || s->done == 3) return;
+  float beta = (float)s->beta;
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+    p[i] = r[i] / d[i] + beta * p[i];
+}
+int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,
+                       double delta, int64_t n, Reduce red2, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_replace, dim3(grid_for(n)), dim3(NTV), 0, st, r32, r64, d, s, delta, n,
+                     red2);
+  hipLaunchKernelGGL(k_pcg_pupdate_force, dim3(grid_for(n)), dim3(NTV), 0, st, p, r32, d, s, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -191,6 +251,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *A
     double rznew = red.result[0], rr = red.result[1];
     s->alpha = alpha_d;
     s->beta = rznew / s->rz;
+    s->rz_old = s->rz;
     s->rz = rznew;
     s->rr = rr;
     s->iters += 1;
@@ -198,6 +259,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *A
     else if (!std::isfinite(rr)) s->done = 3;
     else if (rr <= s->tol2) s->done = 1;
     else if (s->iters >= s->maxit) s->done = 4;
+    else if (rr <= s->upd2) s->done = 5;
   }
 }
 template <typename T>
@@ -352,15 +414,19 @@ template int launch_bc<float>(float *, int, const MeshK<float> &, hipStream_t);
 template int launch_dot2<double>(const double *, const double *, int64_t, Reduce, hipStream_t);
 template int launch_dot2<float>(const float *, const float *, int64_t, Reduce, hipStream_t);
 template int launch_pcg_init<double>(const double *, const double *, double *, PcgDev *, double,
-                                     int, int64_t, Reduce, hipStream_t);
+                                     int, double, int64_t, Reduce, hipStream_t);
 template int launch_pcg_init<float>(const float *, const float *, float *, PcgDev *, double, int,
-                                    int64_t, Reduce, hipStream_t);
+                                    double, int64_t, Reduce, hipStream_t);
 template int launch_pcg_update<double>(double *, double *, const double *, double *,
                                        const double *, PcgDev *, int64_t, Reduce, hipStream_t);
 template int launch_pcg_update<float>(float *, float *, const float *, float *, const float *,
                                       PcgDev *, int64_t, Reduce, hipStream_t);
 template int launch_pcg_pupdate<double>(double *, const double *, const double *, const PcgDev *,
                                         int64_t, hipStream_t);
+template int launch_pcg_pap<double>(const double *, const double *, PcgDev *, int64_t, Reduce,
+                                    hipStream_t);
+template int launch_pcg_pap<float>(const float *, const float *, PcgDev *, int64_t, Reduce,
+                                   hipStream_t);
 template int launch_pcg_pupdate<float>(float *, const float *, const float *, const PcgDev *,
                                        int64_t, hipStream_t);
 

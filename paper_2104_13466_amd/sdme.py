@@ -96,6 +96,7 @@ SIGNATURES = {
                                     _vp, _vp, ctypes.POINTER(Stats), _vp, _sz, _vp], _i),
     "sdme_misfit": ([_vp, _vp, _vp, _vp, _dp, _vp], _i),
     "sdme_axpby": ([_vp, _i64, _d, _vp, _d, _vp, _vp], _i),
+    "sdme_profile": ([_vp, _i, _dp, ctypes.POINTER(_i64)], _i),
 }
 
 
@@ -294,6 +295,14 @@ class Context:
         _chk(self.L.sdme_axpby(self.handle, y.numel(), alpha, _ptr(x), beta, _ptr(y),
                                _stream(stream)), "axpby")
 
+    def profile(self, enable):
+        """Return {fp64_ms, fp64_count, fp32_ms, fp32_count} accumulated since
+        the previous call, then reset and switch PCG-operator timing on/off."""
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int64 * 2)()
+        _chk(self.L.sdme_profile(self.handle, 1 if enable else 0, ms, cnt), "profile")
+        return dict(fp64_ms=ms[0], fp64_count=cnt[0], fp32_ms=ms[1], fp32_count=cnt[1])
+
     def misfit(self, u, target, lam_out, stream=None):
         J = ctypes.c_double()
         _chk(self.L.sdme_misfit(self.handle, _ptr(u), _ptr(target), _ptr(lam_out), ctypes.byref(J),
@@ -302,7 +311,7 @@ class Context:
 
     # ---------------------------------------------------------------- solvers
     def jacobi_pcg(self, mat, prec, b, x, u_lin=None, mass_shift=0.0, mass_only=False, rtol=1e-8,
-                   maxit=100000, inner_rtol=1e-4, stream=None, check=True):
+                   maxit=100000, inner_rtol=1e-2, stream=None, check=True):
         st = Stats()
         ws, nb = self._wsargs(OP_PCG, prec)
         rc = self.L.sdme_jacobi_pcg(self.handle, ctypes.byref(mat), prec, _ptr(u_lin), mass_shift,

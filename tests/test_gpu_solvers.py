@@ -1,0 +1,235 @@
+"""GPU parity of the libsdme solvers and drivers against the FP64 oracle:
+Jacobi-PCG (FP64 and mixed FP32/FP64 defect correction), static Newton,
+Newmark-Newton steps, central-difference steps with penalty contact and
+energies, the power-iteration CFL estimate, and the discrete adjoint behind
+torch.autograd (against the oracle adjoint and central finite differences).
+
+Iterative results cannot match to rounding (atomic scatter order), so they are
+compared by iteration counts (within max(1, 2 %)), by both meeting the
+tolerance, and by solution differences bounded by a multiple of the tolerance.
+"""
+import numpy as np
+import pytest
+
+from oracle import basis as ob
+from oracle import solvers as osv
+from paper_2104_13466_amd import inputs
+from paper_2104_13466_amd.sdme import FP32, FP64, MASK_BC
+from tests.gpu_setup import Pair, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _close_counts(a, b):
+    return abs(a - b) <= max(1, int(0.02 * max(a, b)))
+
+
+@pytest.fixture(scope="module")
+def cube8():
+    # unit cube of 2x2x2 hexahedra, P=3, SDME-H, E=1e3, nu=0.3, clamped x=0
+    return Pair((2, 2, 2), (1.0, 1.0, 1.0), 3, kind=ob.SDME_H, dirichlet=inputs.face_bits(0))
+
+
+def test_pcg_fp64_matches_oracle(cube8):
+    p = cube8
+    u = p.mask * p.rand(1, 1e-3)
+    b = p.mask * inputs.uniform(2, p.N, -1, 1)
+    x = p.zeros()
+    st = p.ctx.jacobi_pcg(p.mat, FP64, p.dev(b), x, u_lin=p.dev(u), rtol=1e-10)
+    xr, its, rel = osv.pcg(p.pb.A(u, 0.0), b, p.pb.diag(u, 0.0), 1e-10, 100000)
+    assert st["rel_residual"] <= 1e-10 and rel <= 1e-10
+    assert _close_counts(st["iterations"], its), (st["iterations"], its)
+    xg = p.host(x)
+    assert relerr(xg, xr) < 1e-8
+    # true residual of the GPU solution, evaluated by the oracle
+    r = b - p.pb.A(u, 0.0)(xg)
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+
+
+def test_pcg_mixed_precision_reaches_fp64_tolerance(cube8):
+    p = cube8
+    u = p.mask * p.rand(3, 1e-3)
+    b = p.mask * inputs.uniform(4, p.N, -1, 1)
+    x = p.zeros()
+    st = p.ctx.jacobi_pcg(p.mat, FP32, p.dev(b), x, u_lin=p.dev(u), rtol=1e-10, inner_rtol=1e-4)
+    assert st["outer"] >= 2 and st["rel_residual"] <= 1e-10
+    xg = p.host(x)
+    r = b - p.pb.A(u, 0.0)(xg)
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+    xr, _, _ = osv.pcg(p.pb.A(u, 0.0), b, p.pb.diag(u, 0.0), 1e-12, 100000)
+    assert relerr(xg, xr) < 1e-8
+
+
+def test_pcg_with_mass_shift_and_mass_only(cube8):
+    p = cube8
+    u = p.mask * p.rand(5, 1e-3)
+    b = p.mask * inputs.uniform(6, p.N, -1, 1)
+    x = p.zeros()
+    st = p.ctx.jacobi_pcg(p.mat, FP64, p.dev(b), x, u_lin=p.dev(u), mass_shift=400.0, rtol=1e-11)
+    xr, its, _ = osv.pcg(p.pb.A(u, 400.0), b, p.pb.diag(u, 400.0), 1e-11, 100000)
+    assert _close_counts(st["iterations"], its)
+    assert relerr(p.host(x), xr) < 1e-9
+    x2 = p.zeros()
+    st = p.ctx.jacobi_pcg(p.mat, FP64, p.dev(b), x2, mass_only=True, rtol=1e-12)
+    xm, its, _ = osv.pcg(p.pb.M, b, p.pb.mass_diag(), 1e-12, 100000)
+    assert _close_counts(st["iterations"], its)
+    assert relerr(p.host(x2), xm) < 1e-10
+
+
+def test_one_newton_step_cube8(cube8):
+    # internal force and tangent at a random state, one Newton step by PCG 1e-10
+    p = cube8
+    u = p.mask * p.rand(7, 1e-3)
+    R = p.zeros()
+    p.ctx.internal_force(p.mat, FP64, p.dev(u), R, flags=MASK_BC)
+    psi = -p.host(R)
+    du = p.zeros()
+    p.ctx.jacobi_pcg(p.mat, FP64, p.dev(psi), du, u_lin=p.dev(u), rtol=1e-10)
+    psi_r = p.mask * (-p.pb.R(u))
+    dur, _, _ = osv.pcg(p.pb.A(u, 0.0), psi_r, p.pb.diag(u, 0.0), 1e-10, 100000)
+    assert relerr(psi, psi_r) < 1e-12
+    assert relerr(p.host(du), dur) < 1e-8
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_newton_static_compression(prec):
+    # unit cube 3x3x3, P=2: clamp z=0, top moved to -0.1, perturbed guess
+    bits = inputs.face_bits(4) | inputs.face_bits(5)
+    p = Pair((3, 3, 3), (1.0, 1.0, 1.0), 2, kind=ob.SDME_H, dirichlet=bits)
+    G = np.zeros((3, 3))
+    G[2, 2] = -0.1
+    u0 = p.ctx.affine_field([0, 0, 0], G) + p.mask * p.rand(8, 1e-3)
+    ud = p.dev(u0)
+    st = p.ctx.newton_static(p.mat, prec, ud, newton_rtol=1e-8, pcg_rtol=1e-8)
+    ur, hist = osv.newton_static(p.pb, u0, np.zeros_like(u0), 1e-8, 1e-8)
+    assert st["newton_rel"] <= 1e-8
+    assert abs(st["newton"] - sum(1 for h in hist if isinstance(h, tuple))) <= 1
+    assert relerr(p.host(ud), ur) < 1e-7
+
+
+def test_newmark_steps_cantilever():
+    # 4x1x1 cantilever (length 4), P=2, clamped x=0, tip traction -z
+    p = Pair((4, 1, 1), (4.0, 1.0, 1.0), 2, kind=ob.SDME_H, dirichlet=inputs.face_bits(0))
+    xf, wf = ob.gauss_legendre(3)
+    Bf, _ = p.basis.eval(xf)
+    fr = p.pb.mesh.vec()
+    p.pb.mesh.face_traction(1, [0, 0, -5.0], Bf, wf, fr)
+    f = p.zeros()
+    p.ctx.face_traction(1, [0, 0, -5.0], f)
+    assert relerr(p.host(f), fr) < 1e-12
+    u, v, a = p.zeros(), p.zeros(), p.zeros()
+    ur, vr, ar = np.zeros(p.N), np.zeros(p.N), np.zeros(p.N)
+    dt = 0.05
+    first = None
+    for n in range(3):
+        s = (n + 1) / 3.0
+        fn = p.zeros()
+        p.ctx.axpby(s, f, 0.0, fn)
+        st = p.ctx.newmark_newton_step(p.mat, FP64, u, v, a, fn, dt, newton_rtol=1e-9,
+                                       pcg_rtol=1e-10)
+        ur, vr, ar, nits, pits = osv.newmark_step(p.pb, ur, vr, ar, s * fr, dt, 1e-9, 1e-10)
+        first = ur.copy() if first is None else first
+        assert abs(st["newton"] - nits) <= 1
+    assert relerr(p.host(u), ur) < 1e-8
+    assert relerr(p.host(v), vr) < 1e-7
+    assert relerr(p.host(a), ar) < 1e-6
+    # mixed precision reaches the same first step
+    u2, v2, a2 = p.zeros(), p.zeros(), p.zeros()
+    fn = p.zeros()
+    p.ctx.axpby(1.0 / 3.0, f, 0.0, fn)
+    p.ctx.newmark_newton_step(p.mat, FP32, u2, v2, a2, fn, dt, newton_rtol=1e-9, pcg_rtol=1e-10)
+    assert relerr(p.host(u2), first) < 1e-8
+
+
+def test_explicit_steps_with_contact_and_energy():
+    # 3x3x2 block, P=2, SDME-M, moving down onto the plane z=0
+    p = Pair((3, 3, 2), (1.0, 1.0, 0.5), 2, kind=ob.SDME_M)
+    v0 = p.ctx.affine_field([0, 0, -1.0], np.zeros((3, 3)))
+    eps = 10 * 1.0e3 / (1.0 / 3)
+    dt = 2e-4
+    xf, wf = ob.gauss_legendre(3)
+    Bf, _ = p.basis.eval(xf)
+    cont = osv.Contact(eps, 0.0, 0.0, Bf, wf)
+    u0 = np.zeros(p.N)
+    up_r = osv.explicit_start(p.pb, u0, v0, np.zeros(p.N), dt, 1e-13, cont)
+    # library start step gives u_1 directly; the oracle start gives u_{-1}
+    u1 = p.zeros()
+    p.ctx.explicit_step(p.mat, FP64, None, p.dev(u0), u1, dt, v0=p.dev(v0), contact=(eps, 0.0),
+                        mass_rtol=1e-13)
+    u1r = osv.explicit_step(p.pb, up_r, u0, np.zeros(p.N), dt, 1e-13, cont)
+    assert relerr(p.host(u1), u1r) < 1e-10
+    prev, cur = p.dev(u0), u1
+    prev_r, cur_r = u0, u1r
+    for n in range(8):
+        nxt = p.zeros()
+        p.ctx.explicit_step(p.mat, FP64, prev, cur, nxt, dt, contact=(eps, 0.0), mass_rtol=1e-13)
+        nxt_r = osv.explicit_step(p.pb, prev_r, cur_r, np.zeros(p.N), dt, 1e-13, cont)
+        prev, cur, prev_r, cur_r = cur, nxt, cur_r, nxt_r
+    assert relerr(p.host(cur), cur_r) < 1e-9
+    nxt = p.zeros()
+    p.ctx.explicit_step(p.mat, FP64, prev, cur, nxt, dt, contact=(eps, 0.0), mass_rtol=1e-13)
+    nxt_r = osv.explicit_step(p.pb, prev_r, cur_r, np.zeros(p.N), dt, 1e-13, cont)
+    ke, se, ce = p.ctx.energies(p.mat, prev, cur, nxt, dt, contact=(eps, 0.0))
+    ker, ser, cer = osv.energies(p.pb, prev_r, cur_r, nxt_r, dt, cont)
+    assert abs(ke - ker) < 1e-8 * ker and abs(se - ser) < 1e-7 * ser and abs(ce - cer) < 1e-7 * cer
+    # FP32 internal force in the step: same trajectory to FP32 accuracy
+    nxt32 = p.zeros()
+    p.ctx.explicit_step(p.mat, FP32, prev, cur, nxt32, dt, contact=(eps, 0.0), mass_rtol=1e-13)
+    assert relerr(p.host(nxt32), nxt_r) < 1e-5
+
+
+def test_lambda_max_matches_dense():
+    p = Pair((2, 1, 1), (1.0, 0.5, 0.5), 2, kind=ob.SDME_M, dirichlet=inputs.face_bits(0))
+    u = p.mask * p.rand(9, 1e-3)
+    x0 = inputs.uniform(10, p.N, -1, 1)
+    lam = p.ctx.lambda_max(p.mat, p.dev(u), p.dev(x0), iters=400, mass_rtol=1e-13)
+    free = np.nonzero(p.mask)[0]
+    N = p.N
+    K = np.zeros((N, N))
+    M = np.zeros((N, N))
+    for j in free:
+        e = np.zeros(N)
+        e[j] = 1
+        K[:, j] = p.pb.A(u, 0.0)(e)
+        M[:, j] = p.pb.M(e)
+    import scipy.linalg
+    ev = scipy.linalg.eigh(K[np.ix_(free, free)], M[np.ix_(free, free)], eigvals_only=True)
+    assert abs(lam - ev[-1]) < 1e-3 * ev[-1]
+
+
+def test_adjoint_gradient_matches_oracle_and_fd():
+    import torch
+
+    from paper_2104_13466_amd.adjoint import RolloutSpec, SdmeExplicitRollout, rollout
+    n, P = (2, 2, 1), 2
+    mu, lam = inputs.lognormal_lame(11, 4, 1.0e3, 0.3)
+    p = Pair(n, (1.0, 1.0, 0.5), P, kind=ob.SDME_M, dirichlet=inputs.face_bits(0), mu=mu, lam=lam)
+    v0 = p.mask * inputs.uniform(12, p.N, -0.3, 0.3)
+    dt, K = 1e-3, 23
+    lam0, mu0 = inputs.lame(1.0e3, 0.3)
+    ref_pb = Pair(n, (1.0, 1.0, 0.5), P, kind=ob.SDME_M, dirichlet=inputs.face_bits(0)).pb
+    target = osv.rollout(ref_pb, np.zeros(p.N), v0, dt, K, 1e-14)[K]
+    spec = RolloutSpec(p.ctx, 1.0, p.zeros(), p.dev(v0), dt, K, p.dev(target), checkpoint=5,
+                       mass_rtol=1e-14)
+    mu_t = p.dev(mu).requires_grad_(True)
+    lam_t = p.dev(lam).requires_grad_(True)
+    J = SdmeExplicitRollout.apply(mu_t, lam_t, spec)
+    J.backward()
+    gm_r, gl_r, Jr = osv.adjoint_gradient(p.pb, np.zeros(p.N), v0, dt, K, target, 1e-14)
+    assert abs(J.item() - Jr) < 1e-9 * Jr
+    assert relerr(p.host(mu_t.grad), gm_r) < 1e-7
+    assert relerr(p.host(lam_t.grad), gl_r) < 1e-7
+    # central differences of the GPU rollout, h = 1e-6 relative
+    with torch.no_grad():
+        for arr, g in ((mu_t, mu_t.grad), (lam_t, lam_t.grad)):
+            for e in range(4):
+                h = 1e-6 * arr[e].item()
+                a = arr.detach().clone()
+                a[e] += h
+                Jp = rollout(spec, a if arr is mu_t else mu_t.detach(),
+                             lam_t.detach() if arr is mu_t else a, keep=False)[0]
+                a[e] -= 2 * h
+                Jm = rollout(spec, a if arr is mu_t else mu_t.detach(),
+                             lam_t.detach() if arr is mu_t else a, keep=False)[0]
+                fd = (Jp - Jm) / (2 * h)
+                assert abs(fd - g[e].item()) < 1e-5 * abs(g[e].item()) + 1e-8 * g.abs().max().item()
