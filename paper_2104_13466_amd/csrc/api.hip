@@ -274,7 +274,7 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
   if (launch_diag<double>(P, c->m64, mat->mu, mat->lam, mass_only ? nullptr : state64,
                           mass_only ? mat->rho : shift * mat->rho, w.d64, 1, st))
     return SDME_EDEVICE;
-  if (launch_bc<double>(w.d64, 1, c->m64, st)) return SDME_EDEVICE;
+  if (launch_bc<double>(w.d64, 1, c->m64, st) || launch_recip(w.d64, N, st)) return SDME_EDEVICE;
   int its = 0;
   double rel = 0;
   if (prec == SDME_FP64) {
@@ -324,8 +324,8 @@ static int ensure_device(sdme_ctx *c) {
   int64_t E = c->E;
   int TS = (int)c->tab_host.size();
   const std::vector<double> &tab = c->tab_host;
-  int nblk = elem_blocks(P, 4, (int)E);
-  int nblk8 = elem_blocks(P, 8, (int)E);
+  int nblk = elem_blocks(P, 4, d->nx, d->ny, d->nz);
+  int nblk8 = elem_blocks(P, 8, d->nx, d->ny, d->nz);
   if (nblk8 > nblk) nblk = nblk8;
   if (nblk < 2 * VEC_BLOCKS) nblk = 2 * VEC_BLOCKS;
   int64_t fb = std::max(std::max(d->nx * d->ny, d->ny * d->nz), d->nx * d->nz);

@@ -80,7 +80,7 @@ int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double 
 #undef C
 }
 
-int elem_blocks(int P, int word, int E) {
+int elem_blocks(int P, int word, int nx, int ny, int nz) {
   int ne = 1;
   switch (P * 10 + (word == 8 ? 1 : 0)) {
 #define NEC(p)                                                        \
@@ -90,7 +90,7 @@ int elem_blocks(int P, int word, int E) {
 #undef NEC
     default: ne = 1;
   }
-  return (E + ne - 1) / ne;
+  return ((nx + ne - 1) / ne) * ny * nz;
 }
 
 template int launch_force<double>(int, const MeshK<double> &, const double *, const double *,

@@ -15,6 +15,16 @@
 #include "sdme_device.h"
 #include "sdme_launch.h"
 
+#ifndef SDME_INNER_STORE
+#define SDME_INNER_STORE 0
+#endif
+#ifndef SDME_WB_MODE
+#define SDME_WB_MODE 2  // 0 stores + atomics in separate loops, 1 atomics only in the same loops, 2 one atomic loop
+#endif
+#ifndef SDME_BND_FLAG
+#define SDME_BND_FLAG 1
+#endif
+
 namespace sdme {
 
 template <int P, int Q, typename T>
@@ -22,12 +32,19 @@ struct EK {
   using Dm = Dims<P, Q, (int)sizeof(T)>;
   static constexpr int n = Dm::n, n3 = Dm::n3, QQ = Dm::QQ, NE = Dm::NE, NT = Dm::NT;
   static constexpr int SA = Dm::SA, SB = Dm::SB, SE = Dm::SE, TS = Dm::TSIZE;
+  static constexpr int TX = Dm::TX, TILE = Dm::TILE;
+  // shared memory words of a block: per-element regions, the tile, tables
+  static constexpr int SMEM = NE * SE + TILE + TS;
 };
 
-// Thread/element coordinates inside a block.
+// Thread/element coordinates inside a block.  Block b owns the run of NE
+// consecutive elements ex = k NE .. k NE + NE - 1 of the x-row (ey, ez), with
+// k = b mod ceil(nx / NE); elements past the end of the row are idle.
 struct Slab {
   int le, t2, i1, i2, e, ex, ey, ez;
+  int x0;     // first slot (x) of the block's tile
   bool valid;
+  bool bnd;   // the block's tile touches a face carrying Dirichlet constraints
 };
 
 template <class K, typename T>
@@ -37,13 +54,27 @@ __device__ __forceinline__ Slab make_slab(const MeshK<T> &m) {
   s.t2 = threadIdx.x % K::QQ;
   s.i1 = s.t2 % K::Dm::Q;
   s.i2 = s.t2 / K::Dm::Q;
-  s.e = blockIdx.x * K::NE + s.le;
-  s.valid = s.e < m.E;
-  int e = s.valid ? s.e : 0;
-  s.ex = e % m.nx;
-  s.ey = (e / m.nx) % m.ny;
-  s.ez = e / (m.nx * m.ny);
+  const int bpr = (m.nx + K::NE - 1) / K::NE;
+  const int k = blockIdx.x % bpr, row = blockIdx.x / bpr;
+  s.ey = row % m.ny;
+  s.ez = row / m.ny;
+  const int ex0 = k * K::NE;
+  s.ex = ex0 + s.le;
+  s.valid = s.ex < m.nx;
+  s.e = (s.ez * m.ny + s.ey) * m.nx + (s.valid ? s.ex : 0);
+  if (!s.valid) s.ex = m.nx - 1;
+  s.x0 = ex0 * K::Dm::P;
+  const uint32_t b = m.bc;
+  const int exl = min(ex0 + K::NE, m.nx) - 1;
+  s.bnd = (ex0 == 0 && (b & 07u)) || (exl == m.nx - 1 && (b & 070u)) ||
+          (s.ey == 0 && (b & 0700u)) || (s.ey == m.ny - 1 && (b & 07000u)) ||
+          (s.ez == 0 && (b & 070000u)) || (s.ez == m.nz - 1 && (b & 0700000u));
   return s;
+}
+
+template <class K>
+__host__ __device__ constexpr int blocks_for(int nx, int ny, int nz) {
+  return ((nx + K::NE - 1) / K::NE) * ny * nz;
 }
 
 template <class K, typename T>
@@ -57,27 +88,32 @@ __device__ __forceinline__ size_t slot_index(const MeshK<T> &m, const Slab &s, i
   return ((size_t)(s.ez * P + c) * m.Ny + (s.ey * P + b)) * m.Nx + (s.ex * P + a);
 }
 
-// Gather one component of v into su[n^3] (zero for constrained DOFs if mask).
+// Cooperative, coalesced load of the block's tile: tile[comp][c][b][x] =
+// v(comp, x0 + x, ey P + b, ez P + c) for x < TX inside the mesh (zero outside
+// and, with mask, on constrained DOFs).
 template <class K, typename T>
-__device__ __forceinline__ void gather_comp(const MeshK<T> &m, const Slab &s, const T *__restrict__ v,
-                                            int comp, bool mask, T *su) {
-  constexpr int n = K::n, P = K::Dm::P;
-  for (int idx = s.t2; idx < K::n3; idx += K::QQ) {
-    int a = idx % n, b = (idx / n) % n, c = idx / (n * n);
+__device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, const T *__restrict__ v,
+                                            bool mask, T *tile) {
+  constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
+  const size_t base = ((size_t)(s.ez * P) * m.Ny + s.ey * P) * m.Nx + s.x0;
+  for (int idx = threadIdx.x; idx < K::TILE; idx += K::NT) {
+    int x = idx % TX, r = idx / TX;  // r = (comp n + c) n + b
+    int b = r % n, c = (r / n) % n, comp = r / (n * n);
     T val = T(0);
-    if (s.valid) {
-      int ix = s.ex * P + a, iy = s.ey * P + b, iz = s.ez * P + c;
-      if (!(mask && is_constrained(m.bc, comp, ix, iy, iz, m.Nx, m.Ny, m.Nz)))
-        val = v[(size_t)comp * m.Nn + ((size_t)iz * m.Ny + iy) * m.Nx + ix];
-    }
-    su[idx] = val;
+    if (s.x0 + x < m.Nx &&
+        !(mask && s.bnd &&
+          is_constrained(m.bc, comp, s.x0 + x, s.ey * P + b, s.ez * P + c, m.Nx, m.Ny, m.Nz)))
+      val = v[(size_t)comp * m.Nn + base + ((size_t)c * m.Ny + b) * m.Nx + x];
+    tile[idx] = val;
   }
 }
 
-// xi1 contraction: st0[c][b][q1] = sum_a B[q1][a] u[c][b][a]; st1 with D.
+// xi1 contraction of one component: st0[c][b][q1] = sum_a B[q1][a] u[c][b][a],
+// st1 with D; su points at the element's first slot in the tile (rows of
+// stride TX).
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T *st, const Slab &s) {
-  constexpr int n = K::n, Q = K::Dm::Q;
+  constexpr int n = K::n, Q = K::Dm::Q, TX = K::TX;
   if (s.i2 < n) {
     T rb[n], rd[n];
 #pragma unroll
@@ -90,7 +126,7 @@ __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T 
       T sb = T(0), sd = T(0);
 #pragma unroll
       for (int a = 0; a < n; a++) {
-        T x = su[(c * n + s.i2) * n + a];
+        T x = su[(c * n + s.i2) * TX + a];
         sb += rb[a] * x;
         if (GRAD) sd += rd[a] * x;
       }
@@ -100,11 +136,11 @@ __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T 
   }
 }
 
-// xi2 contraction into registers: XBB[c] (B in xi1, B in xi2), XBD (B, D),
-// XDB (D, B) at column (q1, q2) = (i1, i2).
+// xi2 contraction into registers at column (q1, q2) = (i1, i2): X[0][c]
+// (B in xi1, B in xi2), X[1][c] (B, D), X[2][c] (D, B).
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, const Slab &s,
-                                       T (&XBB)[K::n], T (&XBD)[K::n], T (&XDB)[K::n]) {
+                                       T (&X)[3][K::n]) {
   constexpr int n = K::n, Q = K::Dm::Q;
   T rb[n], rd[n];
 #pragma unroll
@@ -124,47 +160,59 @@ __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, co
         db += rb[b] * st[n * n * Q + (c * n + b) * Q + s.i1];
       }
     }
-    XBB[c] = bb;
+    X[0][c] = bb;
     if (GRAD) {
-      XBD[c] = bd;
-      XDB[c] = db;
+      X[1][c] = bd;
+      X[2][c] = db;
     }
   }
 }
 
-// Forward pass of all three components of a vector field: registers
-// X[comp][kind][c] with kind 0 = BB, 1 = BD, 2 = DB.  Uses su/st of this
-// element; ends with a barrier.
+// Forward contractions of the three gathered components (tile, synchronised)
+// into X[comp][kind][c].  The xi1 stage of one component overlaps the xi2
+// stage of the previous one through two LDS buffers (one buffer and extra
+// barriers when LDS is short).  Ends after a barrier that follows the last
+// read of the tile.
 template <class K, typename T, bool GRAD>
-__device__ __forceinline__ void forward3(const MeshK<T> &m, const Slab &s, const T *__restrict__ v,
-                                         bool mask, const T *sB, const T *sD, T *su, T *st,
-                                         T (&X)[3][3][K::n]) {
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    gather_comp<K>(m, s, v, i, mask, su);
-    __syncthreads();
-    stage1<K, T, GRAD>(sB, sD, su, st, s);
-    __syncthreads();
-    stage2<K, T, GRAD>(sB, sD, st, s, X[i][0], X[i][1], X[i][2]);
-    __syncthreads();
-  }
+__device__ __forceinline__ void forward_lds(const T *sB, const T *sD, const T *tile, T *st,
+                                            const Slab &s, T (&X)[3][3][K::n]) {
+  constexpr int n = K::n, HB = K::SB / 2, CS = n * n * K::TX;
+  constexpr bool single = K::Dm::DBUF == 1;
+  const T *su = tile + s.le * K::Dm::P;
+  T *st1 = single ? st : st + HB;
+  stage1<K, T, GRAD>(sB, sD, su, st, s);
+  __syncthreads();
+  stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
+  if (single) __syncthreads();
+  stage1<K, T, GRAD>(sB, sD, su + CS, st1, s);
+  __syncthreads();
+  stage2<K, T, GRAD>(sB, sD, st1, s, X[1]);
+  if (single) __syncthreads();
+  stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st, s);
+  __syncthreads();
+  stage2<K, T, GRAD>(sB, sD, st, s, X[2]);
 }
 
-// Gradient (physical) of the field at Gauss point (i1, i2, q3) from X.
+// Physical gradient of the field at Gauss point (i1, i2, q3) from X.
 template <class K, typename T>
 __device__ __forceinline__ void grad_at(const MeshK<T> &m, const T *tab, int q3,
                                         const T (&X)[3][3][K::n], T H[9]) {
   constexpr int n = K::n;
   using Dm = typename K::Dm;
+  T bq[n], dq[n];
+#pragma unroll
+  for (int c = 0; c < n; c++) {
+    bq[c] = tab[Dm::TB + q3 * n + c];
+    dq[c] = tab[Dm::TD + q3 * n + c];
+  }
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T g0 = T(0), g1 = T(0), g2 = T(0);
 #pragma unroll
     for (int c = 0; c < n; c++) {
-      T bq = tab[Dm::TB + q3 * n + c], dq = tab[Dm::TD + q3 * n + c];
-      g0 += bq * X[i][2][c];
-      g1 += bq * X[i][1][c];
-      g2 += dq * X[i][0][c];
+      g0 += bq[c] * X[i][2][c];
+      g1 += bq[c] * X[i][1][c];
+      g2 += dq[c] * X[i][0][c];
     }
     H[i * 3 + 0] = g0 * m.ih[0];
     H[i * 3 + 1] = g1 * m.ih[1];
@@ -207,17 +255,11 @@ __device__ __forceinline__ void accum_at(const T *tab, int q3, const T f[9], con
   }
 }
 
-// Transpose of the xi2 and xi1 contractions for one component and scatter-add
-// into y.  Returns (in dot) sum over this thread's outputs of vdot * y_local
-// when vdot != nullptr (element-local p^T A p).
+// Store the xi3-contracted fluxes of one component (kinds 0 BB-type, 1 BD,
+// 2 DB) into sg[kind][c][q2][q1].
 template <class K, typename T, bool GRAD>
-__device__ __forceinline__ void transpose_scatter(const MeshK<T> &m, const Slab &s, int comp,
-                                                  const T (&A)[3][K::n], const T *sB,
-                                                  const T *sD, T *sg, T *st, T *__restrict__ y,
-                                                  bool mask, const T *__restrict__ vdot,
-                                                  double &dot) {
+__device__ __forceinline__ void write_g(const T (&A)[3][K::n], T *sg, const Slab &s) {
   constexpr int n = K::n, Q = K::Dm::Q, QQ = K::QQ;
-  // A[0] = BB-kind (D or B in xi3 applied), A[1] = BD-kind, A[2] = DB-kind
 #pragma unroll
   for (int c = 0; c < n; c++) {
     sg[(c * Q + s.i2) * Q + s.i1] = A[0][c];
@@ -226,8 +268,15 @@ __device__ __forceinline__ void transpose_scatter(const MeshK<T> &m, const Slab 
       sg[2 * n * QQ + (c * Q + s.i2) * Q + s.i1] = A[2][c];
     }
   }
-  __syncthreads();
-  if (s.i2 < n) {  // thread (q1 = i1, b = i2)
+}
+
+// Transposed xi2 contraction: thread (q1 = i1, b = i2) -> st[c][b][q1] (B in
+// xi1) and st[n^2 Q + ...] (D in xi1).
+template <class K, typename T, bool GRAD>
+__device__ __forceinline__ void stage2t(const T *sB, const T *sD, const T *sg, T *st,
+                                        const Slab &s) {
+  constexpr int n = K::n, Q = K::Dm::Q, QQ = K::QQ;
+  if (s.i2 < n) {
     T cb[Q], cd[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) {
@@ -239,8 +288,7 @@ __device__ __forceinline__ void transpose_scatter(const MeshK<T> &m, const Slab 
       T hb = T(0), hd = T(0);
 #pragma unroll
       for (int q = 0; q < Q; q++) {
-        T g0 = sg[(c * Q + q) * Q + s.i1];
-        hb += cb[q] * g0;
+        hb += cb[q] * sg[(c * Q + q) * Q + s.i1];
         if (GRAD) {
           hb += cd[q] * sg[n * QQ + (c * Q + q) * Q + s.i1];
           hd += cb[q] * sg[2 * n * QQ + (c * Q + q) * Q + s.i1];
@@ -250,15 +298,23 @@ __device__ __forceinline__ void transpose_scatter(const MeshK<T> &m, const Slab 
       if (GRAD) st[n * n * Q + (c * n + s.i2) * Q + s.i1] = hd;
     }
   }
-  __syncthreads();
-  if (s.i1 < n && s.i2 < n) {  // thread (a = i1, b = i2)
+}
+
+// Transposed xi1 contraction of component comp, thread (a = i1, b = i2),
+// added into the block's output tile (LDS atomics: neighbouring elements of
+// the run share their x-faces).
+template <class K, typename T, bool GRAD>
+__device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *sB, const T *sD,
+                                             const T *st, T *tile) {
+  constexpr int n = K::n, Q = K::Dm::Q, P = K::Dm::P, TX = K::TX;
+  if (s.valid && s.i1 < n && s.i2 < n) {
     T cb[Q], cd[Q];
 #pragma unroll
     for (int q = 0; q < Q; q++) {
       cb[q] = sB[q * n + s.i1];
       if (GRAD) cd[q] = sD[q * n + s.i1];
     }
-    constexpr int P = K::Dm::P;
+    T *row = tile + ((comp * n) * n + s.i2) * TX + s.le * P + s.i1;
 #pragma unroll
     for (int c = 0; c < n; c++) {
       T val = T(0);
@@ -267,17 +323,106 @@ __device__ __forceinline__ void transpose_scatter(const MeshK<T> &m, const Slab 
         val += cb[q] * st[(c * n + s.i2) * Q + q];
         if (GRAD) val += cd[q] * st[n * n * Q + (c * n + s.i2) * Q + q];
       }
-      if (s.valid) {
-        int ix = s.ex * P + s.i1, iy = s.ey * P + s.i2, iz = s.ez * P + c;
-        if (!(mask && is_constrained(m.bc, comp, ix, iy, iz, m.Nx, m.Ny, m.Nz))) {
-          size_t gi = (size_t)comp * m.Nn + ((size_t)iz * m.Ny + iy) * m.Nx + ix;
-          atomicAdd(&y[gi], val);
-          if (vdot) dot += (double)vdot[gi] * (double)val;
-        }
-      }
+      atomicAdd(row + c * n * TX, val);
     }
   }
+}
+
+// Write the block's output tile to y.  Slots seen only by this block (rows
+// with 0 < b < P and 0 < c < P, away from the tile's x-ends) are stored; the
+// others, shared with neighbouring rows or blocks, are added atomically.  The
+// two kinds run as two separate loops so that no wave mixes stores and
+// atomics.  Constrained DOFs are skipped when mask is set.  RED adds
+// vdot . tile.
+template <class K, typename T, bool RED>
+__device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s, const T *tile,
+                                               T *__restrict__ y, bool mask,
+                                               const T *__restrict__ vdot, double &dot) {
+  constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
+  constexpr int NI = P - 1;          // interior rows per direction
+  constexpr int XI = TX - 2;         // interior x positions of a row
+  const size_t base = ((size_t)(s.ez * P) * m.Ny + s.ey * P) * m.Nx + s.x0;
+  auto put = [&](int comp, int c, int b, int x, bool own) {
+    int ix = s.x0 + x;
+    if (ix >= m.Nx) return;
+    if (mask && s.bnd &&
+        is_constrained(m.bc, comp, ix, s.ey * P + b, s.ez * P + c, m.Nx, m.Ny, m.Nz))
+      return;
+    size_t gi = (size_t)comp * m.Nn + base + ((size_t)c * m.Ny + b) * m.Nx + x;
+    T val = tile[((comp * n + c) * n + b) * TX + x];
+    if (own)
+      y[gi] = val;
+    else
+      atomicAdd(&y[gi], val);
+    if (RED) dot += (double)vdot[gi] * (double)val;
+  };
+  // owned: interior rows, interior x
+#if SDME_WB_MODE != 2
+  for (int idx = threadIdx.x; idx < 3 * NI * NI * XI; idx += K::NT) {
+    int x = 1 + idx % XI, r = idx / XI;
+    int b = 1 + r % NI, c = 1 + (r / NI) % NI, comp = r / (NI * NI);
+    put(comp, c, b, x, SDME_WB_MODE == 0);
+  }
+  // shared: the x-ends of interior rows, and every slot of boundary rows
+  for (int idx = threadIdx.x; idx < 3 * NI * NI * 2; idx += K::NT) {
+    int e = idx & 1, r = idx >> 1;
+    int b = 1 + r % NI, c = 1 + (r / NI) % NI, comp = r / (NI * NI);
+    int x = e ? TX - 1 : 0;
+    bool own = (x == 0 && s.x0 == 0) || (x == TX - 1 && s.x0 + x == m.Nx - 1);
+    put(comp, c, b, x, own && SDME_WB_MODE == 0);
+  }
+  constexpr int NB = n * n - NI * NI;  // boundary rows per component
+  for (int idx = threadIdx.x; idx < 3 * NB * TX; idx += K::NT) {
+    int x = idx % TX, r = idx / TX;
+    int comp = r / NB, k = r % NB;
+    // k enumerates rows (c, b) with b or c on the element boundary
+    int c, b;
+    if (k < 2 * n) {
+      c = (k < n) ? 0 : P;
+      b = k % n;
+    } else {
+      int kk = k - 2 * n;  // c interior, b in {0, P}
+      c = 1 + kk / 2;
+      b = (kk & 1) ? P : 0;
+    }
+    put(comp, c, b, x, false);
+  }
+#else
+  for (int idx = threadIdx.x; idx < K::TILE; idx += K::NT) {
+    int x = idx % TX, r = idx / TX;
+    int b = r % n, c = (r / n) % n, comp = r / (n * n);
+    put(comp, c, b, x, false);
+  }
+#endif
+}
+
+// Transposes of the xi2 and xi1 contractions for the three components,
+// accumulated into the block's tile (zeroed by the caller after the forward
+// pass), then written back to y.  The flux write of component i+1 overlaps
+// the xi1 stage of component i (sg and the st buffers alternate).
+template <class K, typename T, bool GRAD, bool RED>
+__device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
+                                              const T (&A)[3][3][K::n], const T *sB, const T *sD,
+                                              T *sg, T *st, T *tile, T *__restrict__ y, bool mask,
+                                              const T *__restrict__ vdot, double &dot) {
+  constexpr int HB = (K::Dm::DBUF == 2) ? K::SB / 2 : 0;
+  write_g<K, T, GRAD>(A[0], sg, s);
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    T *sti = st + (i & 1) * HB;
+    stage2t<K, T, GRAD>(sB, sD, sg, sti, s);
+    __syncthreads();
+    if (i < 2) write_g<K, T, GRAD>(A[i + 1], sg, s);
+    stage1t_tile<K, T, GRAD>(s, i, sB, sD, sti, tile);
+    __syncthreads();
+  }
+  tile_writeback<K, T, RED>(m, s, tile, y, mask, vdot, dot);
+}
+
+template <class K, typename T>
+__device__ __forceinline__ void zero_tile(T *tile) {
+  for (int idx = threadIdx.x; idx < K::TILE; idx += K::NT) tile[idx] = T(0);
 }
 
 template <class K, typename T>
@@ -290,14 +435,16 @@ __device__ __forceinline__ void zero_acc(T (&A)[3][3][K::n]) {
       for (int c = 0; c < K::n; c++) A[i][k][c] = T(0);
 }
 
-// Compile-time loop helper.
-template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F &&f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
+// Common kernel prologue: tables and the first field gathered, one barrier.
+#define SDME_PROLOGUE(FIELD, MASK)                                              \
+  __shared__ T smem[K::SMEM];                                                   \
+  T *tile = smem + K::NE * K::SE, *s_tab = tile + K::TILE;                      \
+  load_tables<K>(m, s_tab);                                                     \
+  Slab s = make_slab<K>(m);                                                     \
+  T *su = smem + s.le * K::SE, *st = su + K::SA;                                \
+  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW; \
+  gather_tile<K>(m, s, FIELD, MASK, tile);                                      \
+  __syncthreads();
 
 // ===================================================================== force
 // R(u) (and optionally the linearisation state of u).
@@ -307,20 +454,17 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
                                                            const T *__restrict__ u, T *__restrict__ R,
                                                            T *__restrict__ state, int mask) {
   using K = EK<P, Q, T>;
-  __shared__ T smem[K::NE * K::SE + K::TS];
-  T *s_tab = smem + K::NE * K::SE;
-  load_tables<K>(m, s_tab);
-  Slab s = make_slab<K>(m);
-  T *su = smem + s.le * K::SE, *st = su + K::SA;
-  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW;
-  __syncthreads();
+  SDME_PROLOGUE(u, false)
   T X[3][3][K::n];
-  forward3<K, T, true>(m, s, u, false, sB, sD, su, st, X);
+  forward_lds<K, T, true>(sB, sD, tile, st, s, X);
+  if (OUT) zero_tile<K>(tile);
   T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   if (OUT) zero_acc<K>(A);
   bool bad = false;
+  constexpr int QQQ = Q * Q * Q;
+  T *__restrict__ sp = state + (size_t)(s.valid ? s.e : 0) * 10 * QQQ + s.t2;
 #pragma unroll 1
   for (int q3 = 0; q3 < Q; q3++) {
     T H[9];
@@ -334,10 +478,9 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
       kk.lnJ = T(0);
     }
     if (STORE && s.valid) {
-      size_t base = (size_t)s.e * 10 * Q * Q * Q + (q3 * Q + s.i2) * Q + s.i1;
 #pragma unroll
-      for (int k = 0; k < 9; k++) state[base + (size_t)k * Q * Q * Q] = kk.G[k];
-      state[base + (size_t)9 * Q * Q * Q] = mue - lae * kk.lnJ;
+      for (int k = 0; k < 9; k++) sp[k * QQQ + q3 * K::QQ] = kk.G[k];
+      sp[9 * QQQ + q3 * K::QQ] = mue - lae * kk.lnJ;
     }
     if (OUT) {
       T Pk[9], f[9], mv[3] = {T(0), T(0), T(0)};
@@ -354,44 +497,49 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
   if (bad && s.valid) atomicOr(m.flag, 1);
   if (OUT) {
     double dummy = 0;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-      transpose_scatter<K, T, true>(m, s, i, A[i], sB, sD, su, st, R, mask != 0, nullptr, dummy);
+    transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, R, mask != 0, (const T *)nullptr,
+                                     dummy);
   }
 }
 
 // ============================================================ tangent action
-// y = (K_T + s M) v with K_T from the stored state (REC = false) or from u_lin
-// recomputed at every Gauss point (REC = true).  Optionally accumulates
-// p^T A p (= sum_e v_e^T A_e v_e) into red.
+// y = (K_T + s M) v with K_T from the stored state (REC = false; the state
+// of the next Gauss-point slab is prefetched while the current one is
+// processed) or from u_lin recomputed at every Gauss point (REC = true).
 template <int P, int Q, typename T, bool REC, bool MASS>
 __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     MeshK<T> m, const double *__restrict__ mu, const double *__restrict__ lam,
     const T *__restrict__ ulin, const T *__restrict__ state, T mshift_rho, const T *__restrict__ v,
-    T *__restrict__ y, int mask, Reduce red, int do_red, const int *__restrict__ skip) {
+    T *__restrict__ y, int mask, const int *__restrict__ skip) {
   using K = EK<P, Q, T>;
   if (skip && *skip) return;
-  __shared__ T smem[K::NE * K::SE + K::TS];
-  __shared__ double s_red[(K::NT + 63) / 64];
-  T *s_tab = smem + K::NE * K::SE;
-  load_tables<K>(m, s_tab);
-  Slab s = make_slab<K>(m);
-  T *su = smem + s.le * K::SE, *st = su + K::SA;
-  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW;
-  __syncthreads();
+  SDME_PROLOGUE((REC ? ulin : v), (REC ? false : mask != 0))
   T XU[3][3][K::n];
-  if (REC) forward3<K, T, true>(m, s, ulin, false, sB, sD, su, st, XU);
+  if (REC) {
+    forward_lds<K, T, true>(sB, sD, tile, st, s, XU);
+    __syncthreads();  // the tile is refilled with v below
+    gather_tile<K>(m, s, v, mask != 0, tile);
+    __syncthreads();
+  }
   T X[3][3][K::n];
-  forward3<K, T, true>(m, s, v, mask != 0, sB, sD, su, st, X);
+  forward_lds<K, T, true>(sB, sD, tile, st, s, X);
+  zero_tile<K>(tile);
   T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   zero_acc<K>(A);
   bool bad = false;
+  constexpr int QQQ = Q * Q * Q;
+  const T *__restrict__ sp = state + (size_t)(s.valid ? s.e : 0) * 10 * QQQ + s.t2;
+  T Gn[9], cn = T(0);
+  if (!REC) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) Gn[k] = sp[k * QQQ];
+    cn = sp[9 * QQQ];
+  }
 #pragma unroll 1
   for (int q3 = 0; q3 < Q; q3++) {
     T dF[9], G[9], c1;
-    grad_at<K, T>(m, s_tab, q3, X, dF);
     if (REC) {
       T H[9];
       grad_at<K, T>(m, s_tab, q3, XU, H);
@@ -406,55 +554,79 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
       for (int i = 0; i < 9; i++) G[i] = kk.G[i];
       c1 = mue - lae * kk.lnJ;
     } else {
-      size_t base = (size_t)(s.valid ? s.e : 0) * 10 * Q * Q * Q + (q3 * Q + s.i2) * Q + s.i1;
 #pragma unroll
-      for (int k = 0; k < 9; k++) G[k] = state[base + (size_t)k * Q * Q * Q];
-      c1 = state[base + (size_t)9 * Q * Q * Q];
+      for (int k = 0; k < 9; k++) G[k] = Gn[k];
+      c1 = cn;
+      if (q3 + 1 < Q) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) Gn[k] = sp[k * QQQ + (q3 + 1) * K::QQ];
+        cn = sp[9 * QQQ + (q3 + 1) * K::QQ];
+      }
     }
-    T dP[9], f[9], mv[3];
-    tangent_dp(G, c1, mue, lae, dF, dP);
-    T wq = w12 * s_tab[K::Dm::TW + q3];
+    grad_at<K, T>(m, s_tab, q3, X, dF);
+    T val[3];
+    if (MASS) value_at<K, T>(s_tab, q3, X, val);
+    // dP = mu dF + c1 (G dF G)^T + lam tr(G dF) G^T, one row at a time,
+    // accumulated at once into the transposed xi3 contraction (few live
+    // temporaries)
+    T Am[9];
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+    for (int I = 0; I < 3; I++)
 #pragma unroll
-      for (int J = 0; J < 3; J++) f[i * 3 + J] = dP[i * 3 + J] * wq * m.ih[J];
-    if (MASS) {
-      T val[3];
-      value_at<K, T>(s_tab, q3, X, val);
+      for (int L = 0; L < 3; L++)
+        Am[I * 3 + L] = G[I * 3 + 0] * dF[0 * 3 + L] + G[I * 3 + 1] * dF[1 * 3 + L] +
+                        G[I * 3 + 2] * dF[2 * 3 + L];
+    const T trl = lae * (Am[0] + Am[4] + Am[8]);
+    const T wq = w12 * s_tab[K::Dm::TW + q3];
+    const T s0 = wq * m.ih[0], s1 = wq * m.ih[1], s2 = wq * m.ih[2];
+    T bq[K::n], dq[K::n];
 #pragma unroll
-      for (int i = 0; i < 3; i++) mv[i] = mshift_rho * wq * val[i];
+    for (int c = 0; c < K::n; c++) {
+      bq[c] = s_tab[K::Dm::TB + q3 * K::n + c];
+      dq[c] = s_tab[K::Dm::TD + q3 * K::n + c];
     }
-    accum_at<K, T, true, MASS>(s_tab, q3, f, mv, A);
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      T fr[3];
+#pragma unroll
+      for (int J = 0; J < 3; J++) {
+        T AG = Am[J * 3 + 0] * G[0 * 3 + i] + Am[J * 3 + 1] * G[1 * 3 + i] +
+               Am[J * 3 + 2] * G[2 * 3 + i];
+        fr[J] = mue * dF[i * 3 + J] + c1 * AG + trl * G[J * 3 + i];
+      }
+      fr[0] *= s0;
+      fr[1] *= s1;
+      fr[2] *= s2;
+      const T mv = MASS ? mshift_rho * wq * val[i] : T(0);
+#pragma unroll
+      for (int c = 0; c < K::n; c++) {
+        A[i][2][c] += bq[c] * fr[0];
+        A[i][1][c] += bq[c] * fr[1];
+        A[i][0][c] += dq[c] * fr[2];
+        if (MASS) A[i][0][c] += bq[c] * mv;
+      }
+    }
   }
   if (REC && bad && s.valid) atomicOr(m.flag, 1);
   double dot = 0;
-#pragma unroll
-  for (int i = 0; i < 3; i++)
-    transpose_scatter<K, T, true>(m, s, i, A[i], sB, sD, su, st, y, mask != 0,
-                                  do_red ? v : (const T *)nullptr, dot);
-  if (do_red) {
-    double t = block_sum<K::NT>(dot, s_red);
-    grid_reduce_finish<K::NT>(t, red, s_red, gridDim.x);
-  }
+  transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, y, mask != 0, (const T *)nullptr,
+                                   dot);
 }
 
 // ====================================================================== mass
-template <int P, int Q, typename T>
+// y = rho M v; RED additionally accumulates v^T M v (sum of element-local
+// products) into red.
+template <int P, int Q, typename T, bool RED>
 __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_mass(MeshK<T> m, T rho, const T *__restrict__ v,
                                                           T *__restrict__ y, int mask, Reduce red,
-                                                          int do_red, const int *__restrict__ skip) {
+                                                          const int *__restrict__ skip) {
   using K = EK<P, Q, T>;
   if (skip && *skip) return;
-  __shared__ T smem[K::NE * K::SE + K::TS];
   __shared__ double s_red[(K::NT + 63) / 64];
-  T *s_tab = smem + K::NE * K::SE;
-  load_tables<K>(m, s_tab);
-  Slab s = make_slab<K>(m);
-  T *su = smem + s.le * K::SE, *st = su + K::SA;
-  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW;
-  __syncthreads();
+  SDME_PROLOGUE(v, mask != 0)
   T X[3][3][K::n];
-  forward3<K, T, false>(m, s, v, mask != 0, sB, sD, su, st, X);
+  forward_lds<K, T, false>(sB, sD, tile, st, s, X);
+  zero_tile<K>(tile);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ * rho;
   T A[3][3][K::n];
   zero_acc<K>(A);
@@ -468,11 +640,8 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_mass(MeshK<T> m, T rho, c
     accum_at<K, T, false, true>(s_tab, q3, f, mv, A);
   }
   double dot = 0;
-#pragma unroll
-  for (int i = 0; i < 3; i++)
-    transpose_scatter<K, T, false>(m, s, i, A[i], sB, sD, su, st, y, mask != 0,
-                                   do_red ? v : (const T *)nullptr, dot);
-  if (do_red) {
+  transpose_all<K, T, false, RED>(m, s, A, sB, sD, su, st, tile, y, mask != 0, v, dot);
+  if (RED) {
     double t = block_sum<K::NT>(dot, s_red);
     grid_reduce_finish<K::NT>(t, red, s_red, gridDim.x);
   }
@@ -630,16 +799,10 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_energy(MeshK<double>
                                                                  Reduce red) {
   using T = double;
   using K = EK<P, Q, T>;
-  __shared__ T smem[K::NE * K::SE + K::TS];
   __shared__ double s_red[(K::NT + 63) / 64];
-  T *s_tab = smem + K::NE * K::SE;
-  load_tables<K>(m, s_tab);
-  Slab s = make_slab<K>(m);
-  T *su = smem + s.le * K::SE, *st = su + K::SA;
-  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW;
-  __syncthreads();
+  SDME_PROLOGUE(u, false)
   T X[3][3][K::n];
-  forward3<K, T, true>(m, s, u, false, sB, sD, su, st, X);
+  forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   T mue = s.valid ? mu[s.e] : 0.0, lae = s.valid ? lam[s.e] : 0.0;
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   double acc = 0;
@@ -673,17 +836,14 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_matgrad(
     double *__restrict__ g_mu, double *__restrict__ g_lam) {
   using T = double;
   using K = EK<P, Q, T>;
-  __shared__ T smem[K::NE * K::SE + K::TS];
   __shared__ double s_part[K::NE][2][K::QQ];
-  T *s_tab = smem + K::NE * K::SE;
-  load_tables<K>(m, s_tab);
-  Slab s = make_slab<K>(m);
-  T *su = smem + s.le * K::SE, *st = su + K::SA;
-  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW;
-  __syncthreads();
+  SDME_PROLOGUE(u, false)
   T XU[3][3][K::n], XW[3][3][K::n];
-  forward3<K, T, true>(m, s, u, false, sB, sD, su, st, XU);
-  forward3<K, T, true>(m, s, wv, false, sB, sD, su, st, XW);
+  forward_lds<K, T, true>(sB, sD, tile, st, s, XU);
+  __syncthreads();
+  gather_tile<K>(m, s, wv, false, tile);
+  __syncthreads();
+  forward_lds<K, T, true>(sB, sD, tile, st, s, XW);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   double am = 0, al = 0;
 #pragma unroll 1
@@ -737,7 +897,7 @@ int launch_force_t(const MeshK<T> &m, const double *mu, const double *lam, const
                           T *state, int mask, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
-  dim3 grid((m.E + K::NE - 1) / K::NE), block(K::NT);
+  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   if (R && state)
     hipLaunchKernelGGL((k_force<P, Q, T, true, true>), grid, block, 0, st, m, mu, lam, u, R, state, mask);
   else if (R)
@@ -749,33 +909,38 @@ int launch_force_t(const MeshK<T> &m, const double *mu, const double *lam, const
 
 template <int P, typename T>
 int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
-                            const T *state, T msr, const T *v, T *y, int mask, Reduce red,
-                            int do_red, const int *skip, hipStream_t st) {
+                     const T *state, T msr, const T *v, T *y, int mask, Reduce red, int do_red,
+                     const int *skip, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
-  dim3 grid((m.E + K::NE - 1) / K::NE), block(K::NT);
+  (void)red;
+  if (do_red) return -2;  // p^T A p is taken by a separate dot product
+  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   bool mass = msr != T(0);
   if (ulin) {
     if (mass)
-      hipLaunchKernelGGL((k_tangent<P, Q, T, true, true>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, red, do_red, skip);
+      hipLaunchKernelGGL((k_tangent<P, Q, T, true, true>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
     else
-      hipLaunchKernelGGL((k_tangent<P, Q, T, true, false>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, red, do_red, skip);
+      hipLaunchKernelGGL((k_tangent<P, Q, T, true, false>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
   } else {
     if (mass)
-      hipLaunchKernelGGL((k_tangent<P, Q, T, false, true>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, red, do_red, skip);
+      hipLaunchKernelGGL((k_tangent<P, Q, T, false, true>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
     else
-      hipLaunchKernelGGL((k_tangent<P, Q, T, false, false>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, red, do_red, skip);
+      hipLaunchKernelGGL((k_tangent<P, Q, T, false, false>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int P, typename T>
-int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red,
-                         int do_red, const int *skip, hipStream_t st) {
+int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
+                  const int *skip, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
-  dim3 grid((m.E + K::NE - 1) / K::NE), block(K::NT);
-  hipLaunchKernelGGL((k_mass<P, Q, T>), grid, block, 0, st, m, rho, v, y, mask, red, do_red, skip);
+  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
+  if (do_red)
+    hipLaunchKernelGGL((k_mass<P, Q, T, true>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
+  else
+    hipLaunchKernelGGL((k_mass<P, Q, T, false>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -785,7 +950,7 @@ int launch_diag_t(const MeshK<T> &m, const double *mu, const double *lam, const 
   constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
   static_assert(3 * K::n * K::n * Q <= K::SE, "diag LDS layout");
-  dim3 grid((m.E + K::NE - 1) / K::NE), block(K::NT);
+  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_diag<P, Q, T>), grid, block, 0, st, m, mu, lam, state, msr, d, mask);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -795,7 +960,7 @@ int launch_energy_t(const MeshK<double> &m, const double *mu, const double *lam,
                            const double *u, Reduce red, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, double>;
-  dim3 grid((m.E + K::NE - 1) / K::NE), block(K::NT);
+  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_energy<P, Q>), grid, block, 0, st, m, mu, lam, u, red);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -805,7 +970,7 @@ int launch_matgrad_t(const MeshK<double> &m, const double *u, const double *w, d
                             double *gm, double *gl, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, double>;
-  dim3 grid((m.E + K::NE - 1) / K::NE), block(K::NT);
+  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_matgrad<P, Q>), grid, block, 0, st, m, u, w, scale, gm, gl);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

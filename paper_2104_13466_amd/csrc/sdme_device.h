@@ -17,21 +17,36 @@ struct Dims {
   static constexpr int P = P_, Q = Q_, n = P_ + 1;
   static constexpr int n3 = n * n * n;
   static constexpr int QQ = Q * Q;
-  // LDS words per element: region A holds the gathered component (n^3) in the
-  // forward pass or the xi3-contracted fluxes g1..g3 (3 n Q^2) in the
-  // transpose; region B holds the xi1 partial sums (2 n^2 Q).
-  static constexpr int SA = (n3 > 3 * n * QQ) ? n3 : 3 * n * QQ;
-  static constexpr int SB = 2 * n * n * Q;
-  static constexpr int SE = SA + SB;
-  // elements per block: at most 256 threads and 56 KiB of element LDS
-  static constexpr int NE_T = (256 / QQ) > 0 ? (256 / QQ) : 1;
-  static constexpr int NE_L = (57344 / (SE * WORD)) > 0 ? (57344 / (SE * WORD)) : 1;
-  static constexpr int NE = NE_T < NE_L ? NE_T : NE_L;
-  static constexpr int NT = NE * QQ;
   // tables: B, D (Q n), W (Q), B2, D2, BD (Q n), Bf (n n), Wf (n)
   static constexpr int TB = 0, TD = Q * n, TW = 2 * Q * n, TB2 = 2 * Q * n + Q,
                        TD2 = TB2 + Q * n, TBD = TD2 + Q * n, TBF = TBD + Q * n,
                        TWF = TBF + n * n, TSIZE = TWF + n;
+  // A block owns NE consecutive elements of one x-row of the mesh.  LDS:
+  //  - per element, region A: the xi3-contracted fluxes g1..g3 of one
+  //    component (3 n Q^2); region B: DBUF buffers of xi1 partial sums
+  //    (2 n^2 Q each; two buffers let consecutive components overlap);
+  //  - per block, the tile: the block's slots [3][n][n][TX] with
+  //    TX = NE P + 1 (input gathered once, then the output accumulated).
+  static constexpr int SA = 3 * n * QQ;
+  static constexpr int SB1 = 2 * n * n * Q;
+  static constexpr int NE_T = (256 / QQ) > 0 ? (256 / QQ) : 1;
+  // at most 96 KiB of LDS per block (gfx950 has 160 KiB per CU)
+  static constexpr int LDS_CAP = 98304;
+  static constexpr int lds_words(int ne, int dbuf) {
+    return ne * (SA + dbuf * SB1) + 3 * n * n * (ne * P + 1) + TSIZE;
+  }
+  static constexpr int ne_fit(int dbuf) {
+    int ne = NE_T;
+    while (ne > 1 && lds_words(ne, dbuf) * WORD > LDS_CAP) ne--;
+    return ne;
+  }
+  static constexpr int DBUF = (lds_words(1, 2) * WORD <= LDS_CAP) ? 2 : 1;
+  static constexpr int NE = ne_fit(DBUF);
+  static constexpr int SB = DBUF * SB1;
+  static constexpr int SE = SA + SB;
+  static constexpr int NT = NE * QQ;
+  static constexpr int TX = NE * P + 1;
+  static constexpr int TILE = 3 * n * n * TX;
 };
 
 // Mesh parameters passed by value to every kernel.

@@ -25,7 +25,7 @@ int launch_energy(int P, const MeshK<double> &m, const double *mu, const double 
                   const double *u, Reduce red, hipStream_t st);
 int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double *w, double scale,
                    double *gm, double *gl, hipStream_t st);
-int elem_blocks(int P, int word, int E);
+int elem_blocks(int P, int word, int nx, int ny, int nz);
 
 // ------------------------------------------------------------- face kernels
 // mode 0: traction f += scale * int N t dA on face `face`
@@ -66,6 +66,8 @@ int launch_bc(T *x, int mode, const MeshK<T> &m, hipStream_t st);
 // res[0] = sum x*y, res[1] = sum y*y (double accumulation)
 template <typename T>
 int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st);
+// x = 1 / x (inverse Jacobi diagonal for the PCG kernels)
+int launch_recip(double *x, int64_t n, hipStream_t st);
 // x += scale * double(e)
 int launch_add_scaled_f(double *x, const float *e, double scale, int64_t n, hipStream_t st);
 

@@ -92,6 +92,15 @@ int launch_axpbypcz(double *y, double alpha, const double *x, double beta, doubl
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+__global__ __launch_bounds__(NTV) void k_recip(double *x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
+    x[i] = 1.0 / x[i];
+}
+int launch_recip(double *x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_recip, dim3(grid_for(n)), dim3(NTV), 0, st, x, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 __global__ __launch_bounds__(NTV) void k_add_scaled_f(double *x, const float *e, double scale,
                                                       int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
@@ -136,7 +145,8 @@ int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st) 
 }
 
 // ---------------------------------------------------------------------- PCG
-// init: p = r / d; rz = r.z; rr = r.r; tol2 = rtol^2 rr (r = b at x = 0).
+// The PCG kernels take d = the inverse Jacobi diagonal (z = d r).
+// init: p = d r; rz = r.z; rr = r.r; tol2 = rtol^2 rr (r = b at x = 0).
 template <typename T>
 __global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, PcgDev *s,
                                                   double rtol, int maxit, double delta, int64_t n,
@@ -144,7 +154,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, 
   __shared__ double s_red[NTV / 64];
   double a = 0, b = 0;
   for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
-    T z = r[i] / d[i];
+    T z = r[i] * d[i];
     p[i] = z;
     a += (double)r[i] * (double)z;
     b += (double)r[i] * (double)r[i];
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_replace(float *r32, const double *r
     double rv = r64[i];
     float rf = (float)rv;
     r32[i] = rf;
-    a += (double)rf * (double)(rf / d[i]);
+    a += (double)rf * (double)(rf * d[i]);
     b += rv * rv;
   }
   if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
@@ -216,7 +226,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_pupdate_force(float *p, const float
   if (s->done == 1 || s->done == 3) return;
   float beta = (float)s->beta;
   for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
-    p[i] = r[i] / d[i] + beta * p[i];
+    p[i] = r[i] * d[i] + beta * p[i];
 }
 int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,
                        double delta, int64_t n, Reduce red2, hipStream_t st) {
@@ -227,7 +237,7 @@ int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, 
 }
 
 // update: alpha = rz / pAp; x += alpha p; r -= alpha Ap; Ap = 0;
-// rznew = r.(r/d); rr = r.r; then beta = rznew / rz, convergence test.
+// rznew = r.(d r); rr = r.r; then beta = rznew / rz, convergence test.
 template <typename T>
 __global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d,
                                                     PcgDev *s, int64_t n, Reduce red) {
@@ -243,7 +253,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *A
     T ri = r[i] - alpha * api;
     r[i] = ri;
     Ap[i] = T(0);
-    T z = ri / d[i];
+    T z = ri * d[i];
     a += (double)ri * (double)z;
     b += (double)ri * (double)ri;
   }
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_pupdate(T *p, const T *r, const T *
   if (s->done) return;
   T beta = (T)s->beta;
   for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
-    p[i] = r[i] / d[i] + beta * p[i];
+    p[i] = r[i] * d[i] + beta * p[i];
 }
 template <typename T>
 int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n, hipStream_t st) {
