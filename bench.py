@@ -114,6 +114,18 @@ def kernel_table(ctx, mat, u0):
     return rows
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size (nbytes read + nbytes written per
+    launch): the reference that scales the HBM byte counters of the kernels."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: %d x %d bytes" % (reps, nbytes))
+
+
 def cpu_baseline(w, seconds=10.0):
     """The oracle's direct tangent action timed on the host on a sub-box of the
     workload mesh (same P, Q, basis, element size)."""
@@ -191,6 +203,8 @@ def main():
     ap.add_argument("--increments", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-table", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only the per-operator launches and a 1 GiB copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -205,8 +219,12 @@ def main():
     w, ctx, mat, u0 = setup(a.workload)
     N = 3 * ctx.Nn
     log("mesh %s P=%d: %d DOF, %d elements, %d Gauss points" % (w["n"], w["P"], N, ctx.E, ctx.nqp))
-    if a.kernel_table:
-        kernel_table(ctx, mat, u0)
+    if a.kernel_table or a.profile_kernels:
+        rows = kernel_table(ctx, mat, u0)
+        if a.profile_kernels:
+            copy_calibration()
+            print(json.dumps({"kernel_table": rows}), flush=True)
+            return
     u = u0.clone()
     R = torch.zeros(N, dtype=torch.float64, device="cuda")
     du = torch.zeros_like(R)

@@ -13,36 +13,32 @@ namespace sdme {
 
 constexpr int NTV = VEC_THREADS;
 
-// Two-value deterministic grid reduction.  red.partials holds 2 * gridDim.x
-// doubles; the last block writes res[0], res[1] and returns true in all of
-// its threads.
-__device__ __forceinline__ bool grid_reduce2(double a, double b, Reduce red, double *s_red) {
-  __shared__ bool s_last;
+// Two-value deterministic reductions in two passes: every block of the
+// streaming kernel writes its two block sums to partials[2 b], partials[2 b + 1]
+// (plain stores, no fence or atomic), and a one-block kernel launched after it
+// on the same stream sums the partials in block order.  A device-scope fence
+// per block (a writeback of the XCD's L2) and a counter atomic shared by all
+// blocks cost more than the extra launch.
+__device__ __forceinline__ void block_partials2(double a, double b, Reduce red, double *s_red) {
   double ta = block_sum<NTV>(a, s_red);
   double tb = block_sum<NTV>(b, s_red);
   if (threadIdx.x == 0) {
     red.partials[2 * blockIdx.x] = ta;
     red.partials[2 * blockIdx.x + 1] = tb;
-    __threadfence();
-    unsigned prev = atomicAdd(red.counter, 1u);
-    s_last = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
+}
+
+// Sums of the partials of nb blocks, in block order (one block of NTV
+// threads); valid in thread 0.
+__device__ __forceinline__ void sum_partials2(const double *partials, int nb, double &a, double &b,
+                                              double *s_red) {
   double pa = 0, pb = 0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += NTV) {
-    pa += __builtin_nontemporal_load(&red.partials[2 * i]);
-    pb += __builtin_nontemporal_load(&red.partials[2 * i + 1]);
+  for (int i = threadIdx.x; i < nb; i += NTV) {
+    pa += partials[2 * i];
+    pb += partials[2 * i + 1];
   }
-  pa = block_sum<NTV>(pa, s_red);
-  pb = block_sum<NTV>(pb, s_red);
-  if (threadIdx.x == 0) {
-    red.result[0] = pa;
-    red.result[1] = pb;
-    *red.counter = 0u;
-  }
-  return true;
+  a = block_sum<NTV>(pa, s_red);
+  b = block_sum<NTV>(pb, s_red);
 }
 
 static int grid_for(int64_t n) {
@@ -127,20 +123,53 @@ int launch_bc(T *x, int mode, const MeshK<T> &m, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Streaming loops process U elements per thread and sweep, at i, i + NTV,
+// ..., i + (U - 1) NTV inside a chunk of U NTV elements (coalesced, U loads
+// per array in flight); the chunks are strided over the grid.
+constexpr int U = 4;
+#define SDME_VLOOP(BODY)                                                                    \
+  for (int64_t c0 = (int64_t)blockIdx.x * (NTV * U) + threadIdx.x; c0 < n;                  \
+       c0 += (int64_t)gridDim.x * (NTV * U)) {                                              \
+    if (c0 + (U - 1) * NTV < n) {                                                           \
+      _Pragma("unroll") for (int u = 0; u < U; u++) {                                      \
+        const int64_t i = c0 + u * NTV;                                                     \
+        BODY                                                                                \
+      }                                                                                     \
+    } else {                                                                                \
+      for (int u = 0; u < U; u++) {                                                         \
+        const int64_t i = c0 + u * NTV;                                                     \
+        if (i < n) { BODY }                                                                 \
+      }                                                                                     \
+    }                                                                                       \
+  }
+
+static int grid_for_u(int64_t n) {
+  int64_t b = (n + NTV * U - 1) / (NTV * U);
+  return (int)(b < VEC_BLOCKS ? (b > 0 ? b : 1) : VEC_BLOCKS);
+}
+
 template <typename T>
-__global__ __launch_bounds__(NTV) void k_dot2(const T *x, const T *y, int64_t n, Reduce red) {
+__global__ __launch_bounds__(NTV) void k_dot2(const T *__restrict__ x, const T *__restrict__ y,
+                                              int64_t n, Reduce red) {
   __shared__ double s_red[NTV / 64];
   double a = 0, b = 0;
-  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
-    double xv = (double)x[i], yv = (double)y[i];
-    a += xv * yv;
-    b += yv * yv;
+  SDME_VLOOP(double xv = (double)x[i]; double yv = (double)y[i]; a += xv * yv; b += yv * yv;)
+  block_partials2(a, b, red, s_red);
+}
+__global__ __launch_bounds__(NTV) void k_fin2(Reduce red, int nb) {
+  __shared__ double s_red[NTV / 64];
+  double a, b;
+  sum_partials2(red.partials, nb, a, b, s_red);
+  if (threadIdx.x == 0) {
+    red.result[0] = a;
+    red.result[1] = b;
   }
-  grid_reduce2(a, b, red, s_red);
 }
 template <typename T>
 int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st) {
-  hipLaunchKernelGGL(k_dot2<T>, dim3(grid_for(n)), dim3(NTV), 0, st, x, y, n, red2);
+  const int nb = grid_for_u(n);
+  hipLaunchKernelGGL(k_dot2<T>, dim3(nb), dim3(NTV), 0, st, x, y, n, red2);
+  hipLaunchKernelGGL(k_fin2, dim3(1), dim3(NTV), 0, st, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -148,71 +177,84 @@ int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st) 
 // The PCG kernels take d = the inverse Jacobi diagonal (z = d r).
 // init: p = d r; rz = r.z; rr = r.r; tol2 = rtol^2 rr (r = b at x = 0).
 template <typename T>
-__global__ __launch_bounds__(NTV) void k_pcg_init(const T *r, const T *d, T *p, PcgDev *s,
-                                                  double rtol, int maxit, double delta, int64_t n,
-                                                  Reduce red) {
+__global__ __launch_bounds__(NTV) void k_pcg_init(const T *__restrict__ r, const T *__restrict__ d,
+                                                  T *__restrict__ p, int64_t n, Reduce red) {
   __shared__ double s_red[NTV / 64];
   double a = 0, b = 0;
-  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
-    T z = r[i] * d[i];
-    p[i] = z;
-    a += (double)r[i] * (double)z;
-    b += (double)r[i] * (double)r[i];
-  }
-  if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
-    s->rz = red.result[0];
-    s->rr = red.result[1];
-    s->bb = red.result[1];
-    s->tol2 = rtol * rtol * red.result[1];
-    s->rz_old = red.result[0];
-    s->upd2 = delta * delta * red.result[1];
+  SDME_VLOOP(T ri = r[i]; T z = ri * d[i]; p[i] = z; a += (double)ri * (double)z;
+             b += (double)ri * (double)ri;)
+  block_partials2(a, b, red, s_red);
+}
+__global__ __launch_bounds__(NTV) void k_pcg_init_fin(PcgDev *s, double rtol, int maxit,
+                                                      double delta, Reduce red, int nb) {
+  __shared__ double s_red[NTV / 64];
+  double rz, rr;
+  sum_partials2(red.partials, nb, rz, rr, s_red);
+  if (threadIdx.x == 0) {
+    s->rz = rz;
+    s->rr = rr;
+    s->bb = rr;
+    s->tol2 = rtol * rtol * rr;
+    s->rz_old = rz;
+    s->upd2 = delta * delta * rr;
     s->iters = 0;
     s->maxit = maxit;
     s->pAp = 0;
-    s->done = (s->rr <= s->tol2) ? 1 : (std::isfinite(s->rr) ? 0 : 3);
+    s->done = (rr <= s->tol2) ? 1 : (std::isfinite(rr) ? 0 : 3);
   }
 }
 template <typename T>
 int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int maxit, double delta,
                     int64_t n, Reduce red2, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(grid_for(n)), dim3(NTV), 0, st, r, d, p, s, rtol, maxit,
-                     delta, n, red2);
+  const int nb = grid_for_u(n);
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(nb), dim3(NTV), 0, st, r, d, p, n, red2);
+  hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), dim3(NTV), 0, st, s, rtol, maxit, delta, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTV) void k_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n,
-                                                 Reduce red) {
+__global__ __launch_bounds__(NTV) void k_pcg_pap(const T *__restrict__ p, const T *__restrict__ Ap,
+                                                 PcgDev *s, int64_t n, Reduce red) {
   __shared__ double s_red[NTV / 64];
   if (s->done) return;
   double a = 0;
-  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
-    a += (double)p[i] * (double)Ap[i];
-  if (grid_reduce2(a, 0.0, red, s_red) && threadIdx.x == 0) s->pAp = red.result[0];
+  SDME_VLOOP(a += (double)p[i] * (double)Ap[i];)
+  block_partials2(a, 0.0, red, s_red);
+}
+__global__ __launch_bounds__(NTV) void k_pcg_pap_fin(PcgDev *s, Reduce red, int nb) {
+  __shared__ double s_red[NTV / 64];
+  if (s->done) return;
+  double a, b;
+  sum_partials2(red.partials, nb, a, b, s_red);
+  if (threadIdx.x == 0) s->pAp = a;
 }
 template <typename T>
 int launch_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n, Reduce red2, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_pap<T>, dim3(grid_for(n)), dim3(NTV), 0, st, p, Ap, s, n, red2);
+  const int nb = grid_for_u(n);
+  hipLaunchKernelGGL(k_pcg_pap<T>, dim3(nb), dim3(NTV), 0, st, p, Ap, s, n, red2);
+  hipLaunchKernelGGL(k_pcg_pap_fin, dim3(1), dim3(NTV), 0, st, s, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // Residual replacement of the mixed-precision CG: the recursively updated
 // FP32 residual is replaced by the true FP64 residual b - A x (computed by the
 // caller); the search direction is kept (reliable updates).
-__global__ __launch_bounds__(NTV) void k_pcg_replace(float *r32, const double *r64,
-                                                     const float *d, PcgDev *s, double delta,
-                                                     int64_t n, Reduce red) {
+__global__ __launch_bounds__(NTV) void k_pcg_replace(float *__restrict__ r32,
+                                                     const double *__restrict__ r64,
+                                                     const float *__restrict__ d, int64_t n,
+                                                     Reduce red) {
   __shared__ double s_red[NTV / 64];
   double a = 0, b = 0;
-  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
-    double rv = r64[i];
-    float rf = (float)rv;
-    r32[i] = rf;
-    a += (double)rf * (double)(rf * d[i]);
-    b += rv * rv;
-  }
-  if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
-    double rz = red.result[0], rr = red.result[1];
+  SDME_VLOOP(double rv = r64[i]; float rf = (float)rv; r32[i] = rf;
+             a += (double)rf * (double)(rf * d[i]); b += rv * rv;)
+  block_partials2(a, b, red, s_red);
+}
+__global__ __launch_bounds__(NTV) void k_pcg_replace_fin(PcgDev *s, double delta, Reduce red,
+                                                         int nb) {
+  __shared__ double s_red[NTV / 64];
+  double rz, rr;
+  sum_partials2(red.partials, nb, rz, rr, s_red);
+  if (threadIdx.x == 0) {
     s->beta = rz / s->rz_old;
     s->rz = rz;
     s->rr = rr;
@@ -230,8 +272,9 @@ __global__ __launch_bounds__(NTV) void k_pcg_pupdate_force(float *p, const float
 }
 int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,
                        double delta, int64_t n, Reduce red2, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_replace, dim3(grid_for(n)), dim3(NTV), 0, st, r32, r64, d, s, delta, n,
-                     red2);
+  const int nb = grid_for_u(n);
+  hipLaunchKernelGGL(k_pcg_replace, dim3(nb), dim3(NTV), 0, st, r32, r64, d, n, red2);
+  hipLaunchKernelGGL(k_pcg_replace_fin, dim3(1), dim3(NTV), 0, st, s, delta, red2, nb);
   hipLaunchKernelGGL(k_pcg_pupdate_force, dim3(grid_for(n)), dim3(NTV), 0, st, p, r32, d, s, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -239,27 +282,29 @@ int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, 
 // update: alpha = rz / pAp; x += alpha p; r -= alpha Ap; Ap = 0;
 // rznew = r.(d r); rr = r.r; then beta = rznew / rz, convergence test.
 template <typename T>
-__global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d,
-                                                    PcgDev *s, int64_t n, Reduce red) {
+__global__ __launch_bounds__(NTV) void k_pcg_update(T *__restrict__ x, T *__restrict__ r,
+                                                    const T *__restrict__ p, T *__restrict__ Ap,
+                                                    const T *__restrict__ d, PcgDev *s, int64_t n,
+                                                    Reduce red) {
   __shared__ double s_red[NTV / 64];
   if (s->done) return;
   double pAp = s->pAp;
   double alpha_d = (pAp > 0.0) ? s->rz / pAp : 0.0;
   T alpha = (T)alpha_d;
   double a = 0, b = 0;
-  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV) {
-    T pi = p[i], api = Ap[i];
-    x[i] += alpha * pi;
-    T ri = r[i] - alpha * api;
-    r[i] = ri;
-    Ap[i] = T(0);
-    T z = ri * d[i];
-    a += (double)ri * (double)z;
-    b += (double)ri * (double)ri;
-  }
-  if (grid_reduce2(a, b, red, s_red) && threadIdx.x == 0) {
-    double rznew = red.result[0], rr = red.result[1];
-    s->alpha = alpha_d;
+  SDME_VLOOP(T pi = p[i]; T api = Ap[i]; T xi = x[i]; T ri = r[i]; T di = d[i];
+             x[i] = xi + alpha * pi; ri = ri - alpha * api; r[i] = ri; Ap[i] = T(0);
+             T z = ri * di; a += (double)ri * (double)z; b += (double)ri * (double)ri;)
+  block_partials2(a, b, red, s_red);
+}
+__global__ __launch_bounds__(NTV) void k_pcg_update_fin(PcgDev *s, Reduce red, int nb) {
+  __shared__ double s_red[NTV / 64];
+  if (s->done) return;
+  double rznew, rr;
+  sum_partials2(red.partials, nb, rznew, rr, s_red);
+  if (threadIdx.x == 0) {
+    double pAp = s->pAp;
+    s->alpha = (pAp > 0.0) ? s->rz / pAp : 0.0;
     s->beta = rznew / s->rz;
     s->rz_old = s->rz;
     s->rz = rznew;
@@ -275,21 +320,23 @@ __global__ __launch_bounds__(NTV) void k_pcg_update(T *x, T *r, const T *p, T *A
 template <typename T>
 int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int64_t n,
                       Reduce red2, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(grid_for(n)), dim3(NTV), 0, st, x, r, p, Ap, d, s, n, red2);
+  const int nb = grid_for_u(n);
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(nb), dim3(NTV), 0, st, x, r, p, Ap, d, s, n, red2);
+  hipLaunchKernelGGL(k_pcg_update_fin, dim3(1), dim3(NTV), 0, st, s, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTV) void k_pcg_pupdate(T *p, const T *r, const T *d,
-                                                     const PcgDev *s, int64_t n) {
+__global__ __launch_bounds__(NTV) void k_pcg_pupdate(T *__restrict__ p, const T *__restrict__ r,
+                                                     const T *__restrict__ d, const PcgDev *s,
+                                                     int64_t n) {
   if (s->done) return;
   T beta = (T)s->beta;
-  for (int64_t i = blockIdx.x * (int64_t)NTV + threadIdx.x; i < n; i += (int64_t)gridDim.x * NTV)
-    p[i] = r[i] * d[i] + beta * p[i];
+  SDME_VLOOP(p[i] = r[i] * d[i] + beta * p[i];)
 }
 template <typename T>
 int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_pupdate<T>, dim3(grid_for(n)), dim3(NTV), 0, st, p, r, d, s, n);
+  hipLaunchKernelGGL(k_pcg_pupdate<T>, dim3(grid_for_u(n)), dim3(NTV), 0, st, p, r, d, s, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
