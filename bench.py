@@ -38,10 +38,39 @@ METRIC = "tangent-apply GDOF/s; Newton-PCG solve to 1e-8, mixed-FP32 vs FP64"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK = 157.3   # TFLOP/s (datasheet, dense)
 FP64_PEAK = 78.6
+# flops of the linearised stress dP = mu dF + c1 (G dF G)^T + lam tr(G dF) G^T
+# at one Gauss point, with the 2/h and quadrature-weight scalings
+POINTWISE_FLOPS = 174
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+PROFILE = os.path.join(ROOT, "profiles", "k_tangent_fp32_state__compress_p4.md")
+KERNEL_SOURCES = ("paper_2104_13466_amd/csrc/elem_kernels.hip",
+                  "paper_2104_13466_amd/csrc/sdme_device.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 stored-state tangent kernel from the
+    committed counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
+    None when the element-kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PROFILE):
+            if " = " in line:
+                k, v = line.strip().split(" = ", 1)
+                kv[k] = v
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if kv.get("kernel_sources_sha256") != h.hexdigest()[:16]:
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def setup(name):
@@ -258,6 +287,13 @@ def main():
     k_ms = prof["fp32_ms"] / max(prof["fp32_count"], 1)
     bytes_launch = 40 * ctx.nqp + 8 * N  # state (10 x fp32 per Gauss point) + read v + write y
     achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+    # sum-factorised contractions (forward and transposed, 3 components) plus
+    # the linearised stress at every Gauss point
+    P, Q = w["P"], w["P"] + 2
+    nn = P + 1
+    flops_launch = ctx.E * (2 * 2 * 3 * (2 * Q * nn ** 3 + 3 * Q * Q * nn * nn + 3 * Q ** 3 * nn)
+                            + POINTWISE_FLOPS * Q ** 3)
+    tflops = flops_launch / (k_ms * 1e-3) / 1e12
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 2),
@@ -269,11 +305,15 @@ def main():
                                          w["P"] + 2, N, a.rtol),
                    "dofs": N, "elements": ctx.E, "gauss_points": ctx.nqp},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(),
                      "kernel": "k_tangent<4,6,float,state> (FP32 stored-state tangent action)",
                      "avg_launch_ms": round(k_ms, 4), "launches": prof["fp32_count"],
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "kernel_gdofs": round(N / (k_ms * 1e-3) / 1e9, 2)},
+                     "kernel_gdofs": round(N / (k_ms * 1e-3) / 1e9, 2),
+                     "alu": {"achieved": round(tflops, 2), "peak": FP32_PEAK, "unit": "TFLOP/s",
+                             "frac": round(tflops / FP32_PEAK, 4),
+                             "algorithmic_flops_per_launch": flops_launch}},
         "tangent_applies_per_step": applies / a.steps,
     }
     # FP64 PCG vs mixed on the same Newton iteration (same state, same tolerance)

@@ -15,15 +15,6 @@
 #include "sdme_device.h"
 #include "sdme_launch.h"
 
-#ifndef SDME_INNER_STORE
-#define SDME_INNER_STORE 0
-#endif
-#ifndef SDME_WB_MODE
-#define SDME_WB_MODE 2  // 0 stores + atomics in separate loops, 1 atomics only in the same loops, 2 one atomic loop
-#endif
-#ifndef SDME_BND_FLAG
-#define SDME_BND_FLAG 1
-#endif
 
 namespace sdme {
 
@@ -32,9 +23,16 @@ struct EK {
   using Dm = Dims<P, Q, (int)sizeof(T)>;
   static constexpr int n = Dm::n, n3 = Dm::n3, QQ = Dm::QQ, NE = Dm::NE, NT = Dm::NT;
   static constexpr int SA = Dm::SA, SB = Dm::SB, SE = Dm::SE, TS = Dm::TSIZE;
-  static constexpr int TX = Dm::TX, TILE = Dm::TILE;
-  // shared memory words of a block: per-element regions, the tile, tables
-  static constexpr int SMEM = NE * SE + TILE + TS;
+  static constexpr int TX = Dm::TX, TILE = Dm::TILE, ROWS = Dm::ROWS, RW = Dm::RW;
+  // shared memory words of a block: row offsets, per-element regions, the
+  // tile, tables
+  static constexpr int SMEM = RW + NE * SE + TILE + TS;
+  // Gauss-point slabs of stored state kept in flight by the tangent action
+#ifdef SDME_PF
+  static constexpr int PF = SDME_PF;
+#else
+  static constexpr int PF = 1;
+#endif
 };
 
 // Thread/element coordinates inside a block.  Block b owns the run of NE
@@ -82,29 +80,57 @@ __device__ __forceinline__ void load_tables(const MeshK<T> &m, T *s_tab) {
   for (int i = threadIdx.x; i < K::TS; i += K::NT) s_tab[i] = m.tab[i];
 }
 
+// Global offsets of the rows of the block's tile: row r = (comp n + c) n + b
+// holds the slots (x0 .. x0 + TX - 1, ey P + b, ez P + c) of component comp.
 template <class K, typename T>
-__device__ __forceinline__ size_t slot_index(const MeshK<T> &m, const Slab &s, int a, int b, int c) {
-  constexpr int P = K::Dm::P;
-  return ((size_t)(s.ez * P + c) * m.Ny + (s.ey * P + b)) * m.Nx + (s.ex * P + a);
+__device__ __forceinline__ void tile_rows(const MeshK<T> &m, const Slab &s, int64_t *s_row) {
+  constexpr int n = K::n, P = K::Dm::P;
+  for (int r = threadIdx.x; r < K::ROWS; r += K::NT) {
+    int b = r % n, c = (r / n) % n, comp = r / (n * n);
+    s_row[r] = (int64_t)comp * m.Nn + ((int64_t)(s.ez * P + c) * m.Ny + (s.ey * P + b)) * m.Nx + s.x0;
+  }
+}
+
+// Visit the tile slots idx = r TX + x, idx = threadIdx.x + k NT, with the
+// (row, x) pair advanced incrementally (no divisions in the loop).
+template <class K, typename F>
+__device__ __forceinline__ void tile_for(F &&f) {
+  constexpr int TX = K::TX, NT = K::NT, DX = NT % TX, DR = NT / TX;
+  int x = threadIdx.x % TX, r = threadIdx.x / TX;
+  for (int idx = threadIdx.x; idx < K::TILE; idx += NT) {
+    f(idx, r, x);
+    x += DX;
+    r += DR;
+    if (x >= TX) {
+      x -= TX;
+      r += 1;
+    }
+  }
+}
+
+// Is slot x of tile row r a constrained DOF (only blocks with s.bnd)?
+template <class K, typename T>
+__device__ __forceinline__ bool tile_constrained(const MeshK<T> &m, const Slab &s, int r, int x) {
+  constexpr int n = K::n, P = K::Dm::P;
+  int b = r % n, c = (r / n) % n, comp = r / (n * n);
+  return is_constrained(m.bc, comp, s.x0 + x, s.ey * P + b, s.ez * P + c, m.Nx, m.Ny, m.Nz);
 }
 
 // Cooperative, coalesced load of the block's tile: tile[comp][c][b][x] =
 // v(comp, x0 + x, ey P + b, ez P + c) for x < TX inside the mesh (zero outside
 // and, with mask, on constrained DOFs).
 template <class K, typename T>
-__device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, const T *__restrict__ v,
-                                            bool mask, T *tile) {
-  constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
-  const size_t base = ((size_t)(s.ez * P) * m.Ny + s.ey * P) * m.Nx + s.x0;
-  for (int idx = threadIdx.x; idx < K::TILE; idx += K::NT) {
-    int x = idx % TX, r = idx / TX;  // r = (comp n + c) n + b
-    int b = r % n, c = (r / n) % n, comp = r / (n * n);
-    T val = T(0);
-    if (s.x0 + x < m.Nx &&
-        !(mask && s.bnd &&
-          is_constrained(m.bc, comp, s.x0 + x, s.ey * P + b, s.ez * P + c, m.Nx, m.Ny, m.Nz)))
-      val = v[(size_t)comp * m.Nn + base + ((size_t)c * m.Ny + b) * m.Nx + x];
-    tile[idx] = val;
+__device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, const int64_t *s_row,
+                                            const T *__restrict__ v, bool mask, T *tile) {
+  const int xe = m.Nx - s.x0;  // tile slots x < xe lie inside the mesh
+  if (mask && s.bnd) {
+    tile_for<K>([&](int idx, int r, int x) {
+      T val = T(0);
+      if (x < xe && !tile_constrained<K>(m, s, r, x)) val = v[s_row[r] + x];
+      tile[idx] = val;
+    });
+  } else {
+    tile_for<K>([&](int idx, int r, int x) { tile[idx] = x < xe ? v[s_row[r] + x] : T(0); });
   }
 }
 
@@ -328,72 +354,25 @@ __device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *s
   }
 }
 
-// Write the block's output tile to y.  Slots seen only by this block (rows
-// with 0 < b < P and 0 < c < P, away from the tile's x-ends) are stored; the
-// others, shared with neighbouring rows or blocks, are added atomically.  The
-// two kinds run as two separate loops so that no wave mixes stores and
-// atomics.  Constrained DOFs are skipped when mask is set.  RED adds
+// Add the block's output tile to y with hardware FP atomics (slots on the
+// tile's faces are shared with neighbouring blocks; interior slots are not,
+// but one uniform atomic loop is faster than separate store and atomic
+// loops).  Constrained DOFs are skipped when mask is set.  RED adds
 // vdot . tile.
 template <class K, typename T, bool RED>
-__device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s, const T *tile,
+__device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s,
+                                               const int64_t *s_row, const T *tile,
                                                T *__restrict__ y, bool mask,
                                                const T *__restrict__ vdot, double &dot) {
-  constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
-  constexpr int NI = P - 1;          // interior rows per direction
-  constexpr int XI = TX - 2;         // interior x positions of a row
-  const size_t base = ((size_t)(s.ez * P) * m.Ny + s.ey * P) * m.Nx + s.x0;
-  auto put = [&](int comp, int c, int b, int x, bool own) {
-    int ix = s.x0 + x;
-    if (ix >= m.Nx) return;
-    if (mask && s.bnd &&
-        is_constrained(m.bc, comp, ix, s.ey * P + b, s.ez * P + c, m.Nx, m.Ny, m.Nz))
-      return;
-    size_t gi = (size_t)comp * m.Nn + base + ((size_t)c * m.Ny + b) * m.Nx + x;
-    T val = tile[((comp * n + c) * n + b) * TX + x];
-    if (own)
-      y[gi] = val;
-    else
-      atomicAdd(&y[gi], val);
+  const int xe = m.Nx - s.x0;
+  const bool chk = mask && s.bnd;
+  tile_for<K>([&](int idx, int r, int x) {
+    if (x >= xe || (chk && tile_constrained<K>(m, s, r, x))) return;
+    const int64_t gi = s_row[r] + x;
+    const T val = tile[idx];
+    atomicAdd(&y[gi], val);
     if (RED) dot += (double)vdot[gi] * (double)val;
-  };
-  // owned: interior rows, interior x
-#if SDME_WB_MODE != 2
-  for (int idx = threadIdx.x; idx < 3 * NI * NI * XI; idx += K::NT) {
-    int x = 1 + idx % XI, r = idx / XI;
-    int b = 1 + r % NI, c = 1 + (r / NI) % NI, comp = r / (NI * NI);
-    put(comp, c, b, x, SDME_WB_MODE == 0);
-  }
-  // shared: the x-ends of interior rows, and every slot of boundary rows
-  for (int idx = threadIdx.x; idx < 3 * NI * NI * 2; idx += K::NT) {
-    int e = idx & 1, r = idx >> 1;
-    int b = 1 + r % NI, c = 1 + (r / NI) % NI, comp = r / (NI * NI);
-    int x = e ? TX - 1 : 0;
-    bool own = (x == 0 && s.x0 == 0) || (x == TX - 1 && s.x0 + x == m.Nx - 1);
-    put(comp, c, b, x, own && SDME_WB_MODE == 0);
-  }
-  constexpr int NB = n * n - NI * NI;  // boundary rows per component
-  for (int idx = threadIdx.x; idx < 3 * NB * TX; idx += K::NT) {
-    int x = idx % TX, r = idx / TX;
-    int comp = r / NB, k = r % NB;
-    // k enumerates rows (c, b) with b or c on the element boundary
-    int c, b;
-    if (k < 2 * n) {
-      c = (k < n) ? 0 : P;
-      b = k % n;
-    } else {
-      int kk = k - 2 * n;  // c interior, b in {0, P}
-      c = 1 + kk / 2;
-      b = (kk & 1) ? P : 0;
-    }
-    put(comp, c, b, x, false);
-  }
-#else
-  for (int idx = threadIdx.x; idx < K::TILE; idx += K::NT) {
-    int x = idx % TX, r = idx / TX;
-    int b = r % n, c = (r / n) % n, comp = r / (n * n);
-    put(comp, c, b, x, false);
-  }
-#endif
+  });
 }
 
 // Transposes of the xi2 and xi1 contractions for the three components,
@@ -403,7 +382,8 @@ __device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s,
 template <class K, typename T, bool GRAD, bool RED>
 __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
                                               const T (&A)[3][3][K::n], const T *sB, const T *sD,
-                                              T *sg, T *st, T *tile, T *__restrict__ y, bool mask,
+                                              T *sg, T *st, T *tile, const int64_t *s_row,
+                                              T *__restrict__ y, bool mask,
                                               const T *__restrict__ vdot, double &dot) {
   constexpr int HB = (K::Dm::DBUF == 2) ? K::SB / 2 : 0;
   write_g<K, T, GRAD>(A[0], sg, s);
@@ -417,7 +397,7 @@ __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
     stage1t_tile<K, T, GRAD>(s, i, sB, sD, sti, tile);
     __syncthreads();
   }
-  tile_writeback<K, T, RED>(m, s, tile, y, mask, vdot, dot);
+  tile_writeback<K, T, RED>(m, s, s_row, tile, y, mask, vdot, dot);
 }
 
 template <class K, typename T>
@@ -435,16 +415,23 @@ __device__ __forceinline__ void zero_acc(T (&A)[3][3][K::n]) {
       for (int c = 0; c < K::n; c++) A[i][k][c] = T(0);
 }
 
-// Common kernel prologue: tables and the first field gathered, one barrier.
-#define SDME_PROLOGUE(FIELD, MASK)                                              \
-  __shared__ T smem[K::SMEM];                                                   \
-  T *tile = smem + K::NE * K::SE, *s_tab = tile + K::TILE;                      \
+// Common kernel prologue: tables, slab coordinates and tile row offsets
+// (SDME_SETUP, ends with a barrier), then the first field gathered into the
+// tile (SDME_GATHER, ends with a barrier).
+#define SDME_SETUP                                                              \
+  __shared__ __align__(16) T smem[K::SMEM];                                     \
+  int64_t *s_row = (int64_t *)smem;                                             \
+  T *tile = smem + K::RW + K::NE * K::SE, *s_tab = tile + K::TILE;              \
   load_tables<K>(m, s_tab);                                                     \
   Slab s = make_slab<K>(m);                                                     \
-  T *su = smem + s.le * K::SE, *st = su + K::SA;                                \
+  tile_rows<K>(m, s, s_row);                                                    \
+  T *su = smem + K::RW + s.le * K::SE, *st = su + K::SA;                        \
   const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW; \
-  gather_tile<K>(m, s, FIELD, MASK, tile);                                      \
   __syncthreads();
+#define SDME_GATHER(FIELD, MASK)                                                \
+  gather_tile<K>(m, s, s_row, FIELD, MASK, tile);                               \
+  __syncthreads();
+#define SDME_PROLOGUE(FIELD, MASK) SDME_SETUP SDME_GATHER(FIELD, MASK)
 
 // ===================================================================== force
 // R(u) (and optionally the linearisation state of u).
@@ -497,14 +484,14 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
   if (bad && s.valid) atomicOr(m.flag, 1);
   if (OUT) {
     double dummy = 0;
-    transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, R, mask != 0, (const T *)nullptr,
+    transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, s_row, R, mask != 0, (const T *)nullptr,
                                      dummy);
   }
 }
 
 // ============================================================ tangent action
 // y = (K_T + s M) v with K_T from the stored state (REC = false; the state
-// of the next Gauss-point slab is prefetched while the current one is
+// of the next Gauss-point slabs is in flight while the current one is
 // processed) or from u_lin recomputed at every Gauss point (REC = true).
 template <int P, int Q, typename T, bool REC, bool MASS>
 __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
@@ -513,30 +500,36 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     T *__restrict__ y, int mask, const int *__restrict__ skip) {
   using K = EK<P, Q, T>;
   if (skip && *skip) return;
-  SDME_PROLOGUE((REC ? ulin : v), (REC ? false : mask != 0))
+  SDME_SETUP
+  // stored state: the first PD Gauss-point slabs are requested before the
+  // gather so that their latency hides behind the forward contractions; the
+  // loop keeps PD slabs in flight
+  constexpr int QQQ = Q * Q * Q;
+  constexpr int PD = REC ? 1 : (Q < K::PF ? Q : K::PF);
+  const T *__restrict__ sp = state + (size_t)(s.valid ? s.e : 0) * 10 * QQQ + s.t2;
+  T Gb[PD][10];
+  if (!REC) {
+#pragma unroll
+    for (int d = 0; d < PD; d++)
+#pragma unroll
+      for (int k = 0; k < 10; k++) Gb[d][k] = sp[k * QQQ + d * K::QQ];
+  }
+  const T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
+  SDME_GATHER((REC ? ulin : v), (REC ? false : mask != 0))
   T XU[3][3][K::n];
   if (REC) {
     forward_lds<K, T, true>(sB, sD, tile, st, s, XU);
     __syncthreads();  // the tile is refilled with v below
-    gather_tile<K>(m, s, v, mask != 0, tile);
+    gather_tile<K>(m, s, s_row, v, mask != 0, tile);
     __syncthreads();
   }
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   zero_tile<K>(tile);
-  T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   zero_acc<K>(A);
   bool bad = false;
-  constexpr int QQQ = Q * Q * Q;
-  const T *__restrict__ sp = state + (size_t)(s.valid ? s.e : 0) * 10 * QQQ + s.t2;
-  T Gn[9], cn = T(0);
-  if (!REC) {
-#pragma unroll
-    for (int k = 0; k < 9; k++) Gn[k] = sp[k * QQQ];
-    cn = sp[9 * QQQ];
-  }
 #pragma unroll 1
   for (int q3 = 0; q3 < Q; q3++) {
     T dF[9], G[9], c1;
@@ -555,12 +548,15 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
       c1 = mue - lae * kk.lnJ;
     } else {
 #pragma unroll
-      for (int k = 0; k < 9; k++) G[k] = Gn[k];
-      c1 = cn;
-      if (q3 + 1 < Q) {
+      for (int k = 0; k < 9; k++) G[k] = Gb[0][k];
+      c1 = Gb[0][9];
 #pragma unroll
-        for (int k = 0; k < 9; k++) Gn[k] = sp[k * QQQ + (q3 + 1) * K::QQ];
-        cn = sp[9 * QQQ + (q3 + 1) * K::QQ];
+      for (int d = 0; d + 1 < PD; d++)
+#pragma unroll
+        for (int k = 0; k < 10; k++) Gb[d][k] = Gb[d + 1][k];
+      if (q3 + PD < Q) {
+#pragma unroll
+        for (int k = 0; k < 10; k++) Gb[PD - 1][k] = sp[k * QQQ + (q3 + PD) * K::QQ];
       }
     }
     grad_at<K, T>(m, s_tab, q3, X, dF);
@@ -609,7 +605,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   }
   if (REC && bad && s.valid) atomicOr(m.flag, 1);
   double dot = 0;
-  transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, y, mask != 0, (const T *)nullptr,
+  transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0, (const T *)nullptr,
                                    dot);
 }
 
@@ -640,7 +636,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_mass(MeshK<T> m, T rho, c
     accum_at<K, T, false, true>(s_tab, q3, f, mv, A);
   }
   double dot = 0;
-  transpose_all<K, T, false, RED>(m, s, A, sB, sD, su, st, tile, y, mask != 0, v, dot);
+  transpose_all<K, T, false, RED>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0, v, dot);
   if (RED) {
     double t = block_sum<K::NT>(dot, s_red);
     grid_reduce_finish<K::NT>(t, red, s_red, gridDim.x);
@@ -841,7 +837,7 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_matgrad(
   T XU[3][3][K::n], XW[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, XU);
   __syncthreads();
-  gather_tile<K>(m, s, wv, false, tile);
+  gather_tile<K>(m, s, s_row, wv, false, tile);
   __syncthreads();
   forward_lds<K, T, true>(sB, sD, tile, st, s, XW);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;

@@ -26,14 +26,17 @@ struct Dims {
   //    component (3 n Q^2); region B: DBUF buffers of xi1 partial sums
   //    (2 n^2 Q each; two buffers let consecutive components overlap);
   //  - per block, the tile: the block's slots [3][n][n][TX] with
-  //    TX = NE P + 1 (input gathered once, then the output accumulated).
+  //    TX = NE P + 1 (input gathered once, then the output accumulated),
+  //    and the 64-bit global offsets of its 3 n^2 rows (RW words).
   static constexpr int SA = 3 * n * QQ;
   static constexpr int SB1 = 2 * n * n * Q;
   static constexpr int NE_T = (256 / QQ) > 0 ? (256 / QQ) : 1;
+  static constexpr int ROWS = 3 * n * n;
+  static constexpr int RW = ROWS * 8 / WORD;
   // at most 96 KiB of LDS per block (gfx950 has 160 KiB per CU)
   static constexpr int LDS_CAP = 98304;
   static constexpr int lds_words(int ne, int dbuf) {
-    return ne * (SA + dbuf * SB1) + 3 * n * n * (ne * P + 1) + TSIZE;
+    return ne * (SA + dbuf * SB1) + 3 * n * n * (ne * P + 1) + TSIZE + RW;
   }
   static constexpr int ne_fit(int dbuf) {
     int ne = NE_T;
