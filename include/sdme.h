@@ -15,9 +15,11 @@
  *    Arguments are validated on the host before any launch.
  *  - "dev" pointers are device (HBM) pointers owned by the caller; "host"
  *    pointers are host memory owned by the caller.  The library never frees a
- *    caller buffer.  sdme_create allocates one small device block (reduction
- *    partials and solver scalars, O(number of elements) bytes) and a few bytes
- *    of pinned host memory, released by sdme_destroy.  Large scratch (solver
+ *    caller buffer.  A context allocates one small device block (basis
+ *    tables, reduction partials and solver scalars, O(number of elements)
+ *    bytes) and a few bytes of pinned host memory on the first call that
+ *    touches the device, on the device current at that call; both are
+ *    released by sdme_destroy.  Large scratch (solver
  *    vectors, linearisation state) is passed in by the caller as a workspace
  *    of at least sdme_workspace_bytes() bytes.
  *  - Vectors are structure-of-arrays [3][Nn]: component c of global slot g at
@@ -109,10 +111,11 @@ typedef struct {
   uint32_t dirichlet; /* bit (face*3 + comp): faces 0 x=0, 1 x=max, 2 y=0, 3 y=max, 4 z=0, 5 z=max */
 } sdme_mesh_desc;
 
-/* Create a context for a structured box mesh on the current HIP device.  The
- * basis is built on the host (sdme_basis_build) and its tables are uploaded
- * to the context's device block.  Errors: SDME_EINVAL, SDME_EEIG,
- * SDME_EDEVICE. */
+/* Create a context for a structured box mesh.  The basis is built on the
+ * host (sdme_basis_build) at once; its tables are uploaded to the context's
+ * device block by the first device call (host-only queries such as
+ * sdme_sizes and sdme_gather_indices never touch the device).  Meshes need
+ * 3*Nn < 2^31.  Errors: SDME_EINVAL, SDME_EEIG. */
 int sdme_create(const sdme_mesh_desc *desc, sdme_ctx **out);
 int sdme_destroy(sdme_ctx *ctx);
 
@@ -262,9 +265,19 @@ int sdme_jacobi_pcg(sdme_ctx *ctx, const sdme_material *mat, int prec, const dou
                     int maxit, double inner_rtol, sdme_stats *stats, void *ws, size_t ws_bytes,
                     void *stream);
 
-/* Static Newton-Raphson for R(u) = f_ext (f_ext nullable = 0): K_T du = psi,
- * stop at ||psi||/||psi_0|| <= newton_rtol.  u: dev double [3][Nn], in/out
- * (prescribed values on constrained DOFs are kept).  Synchronises. */
+/*
+ * sdme_newton_static -- Newton-Raphson for R(u) = f_ext (Section 3, the
+ * linearised virtual work with the effective stiffness K_T), f_ext nullable
+ * (= 0): K_T(u) du = psi = f_ext - R(u) by sdme_jacobi_pcg (inner_rtol 1e-2
+ * when prec = SDME_FP32), u += du, until ||psi||_2 <= newton_rtol ||psi_0||_2.
+ * u: dev double [3][Nn], in/out (prescribed values on constrained DOFs are
+ * kept).  If an update inverts an element (det F <= 0) the increment is halved
+ * (up to 20 times).  If PCG meets non-positive curvature (K_T not positive
+ * definite at an iterate) after at least one iteration, the CG iterate reached
+ * so far is taken as du (truncated Newton-CG).  Synchronises.  Errors:
+ * SDME_ENOCONV (max_newton or max_pcg), SDME_EJAC, SDME_EBREAKDOWN (at the
+ * first PCG iteration), SDME_ENOMEM.
+ */
 int sdme_newton_static(sdme_ctx *ctx, const sdme_material *mat, int prec, double *u,
                        const double *f_ext, double newton_rtol, double pcg_rtol, int max_newton,
                        int max_pcg, sdme_stats *stats, void *ws, size_t ws_bytes, void *stream);
@@ -277,7 +290,8 @@ int sdme_newton_static(sdme_ctx *ctx, const sdme_material *mat, int prec, double
  *   b3 = 1/(2 beta) - 1;  then a_{n+1} = b1 (u - u_n) - b2 v_n - b3 a_n,
  *   v_{n+1} = v_n + dt ((1-gamma) a_n + gamma a_{n+1}).
  * u, v, a: dev double [3][Nn], in (step n) / out (step n+1).  f_next
- * nullable.  Synchronises.
+ * nullable.  Predictor u = u_n; damping and truncation as in
+ * sdme_newton_static.  Synchronises.
  */
 int sdme_newmark_newton_step(sdme_ctx *ctx, const sdme_material *mat, int prec, double *u,
                              double *v, double *a, const double *f_next, double dt, double beta,

@@ -262,7 +262,8 @@ void plan_lin(sdme_ctx *c, int prec, bool need_state32, Bump &b, LinWs &w) {
 // Solve (K_T + shift M) x = b (or M x = b) given an FP64 stored state.
 int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *state64,
                  double shift, bool mass_only, const double *b, double *x, double rtol, int maxit,
-                 double inner_rtol, LinWs &w, sdme_stats *stats, hipStream_t st) {
+                 double inner_rtol, LinWs &w, sdme_stats *stats, hipStream_t st,
+                 int *its_out = nullptr) {
   int64_t N = 3 * c->Nn;
   int P = c->P;
   // masked right-hand side
@@ -284,6 +285,7 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
       stats->iterations += its;
       stats->rel_residual = rel;
     }
+    if (its_out) *its_out = its;
     return rc;
   }
   // mixed: FP32 PCG (FP32 state, operator and vectors, FP64 dots) with FP64
@@ -297,11 +299,16 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
   Replace rep{&op64, x, w.r64, w.Ap64, w.bm, inner_rtol, 0};
   int rc = pcg_core<float>(c, mat, op32, w.b32, w.e32, w.d32, rtol, maxit, w.r32, w.p32, w.Ap32, 1,
                            &its, &rel, st, &rep);
+  // on an early stop the FP32 part accumulated since the last replacement
+  // still belongs to the iterate
+  if ((rc == SDME_EBREAKDOWN || rc == SDME_ENOCONV) && launch_add_scaled_f(x, w.e32, 1.0, N, st))
+    return SDME_EDEVICE;
   if (stats) {
     stats->iterations += its;
     stats->outer += rep.count;
     stats->rel_residual = rel;
   }
+  if (its_out) *its_out = its;
   return rc;
 }
 
@@ -873,8 +880,13 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
     if (stats) stats->newton_rel = psi0 > 0 ? nrm / psi0 : 0.0;
     if (nrm <= newton_rtol * psi0 || nrm == 0.0) break;
     if (k >= max_newton) return SDME_ENOCONV;
+    int lin_its = 0;
     rc = solve_linear(c, mat, prec, state64, shift, false, psi, du, pcg_rtol, max_pcg, 1e-2, w,
-                      stats, st);
+                      stats, st, &lin_its);
+    // Non-positive curvature met inside PCG (an iterate where K_T is not
+    // positive definite): take the CG iterate reached before it as the
+    // increment (truncated Newton-CG); the next Newton iteration re-linearises.
+    if (rc == SDME_EBREAKDOWN && lin_its > 0) rc = SDME_OK;
     if (rc) return rc;
     if (launch_axpby(u, 1.0, du, 1.0, N, st)) return SDME_EDEVICE;
     if (stats) stats->newton++;

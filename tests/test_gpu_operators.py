@@ -1,9 +1,9 @@
 """GPU parity of the libsdme element operators against the FP64 oracle, element
 by element on the same seeded inputs: internal force, tangent action (stored
 state and recomputed, with mass shift, masked), mass, Jacobi diagonal, strain
-energy, material sensitivities, face traction and penalty contact.  Meshes span
-several blocks with a ragged tail; every order P = 1..8 and every basis kind
-is covered.  Tolerances: 1e-12 (FP64), 1e-5 (FP32) relative in the max norm."""
+energy, material sensitivities, face traction and penalty contact.  Mesh rows
+span several element blocks with a ragged tail; every order P = 1..8 and every
+basis kind is covered; Dirichlet faces touch both ends of the rows.  Tolerances: 1e-12 (FP64), 1e-5 (FP32) relative in the max norm."""
 import numpy as np
 import pytest
 
@@ -16,14 +16,17 @@ pytestmark = pytest.mark.gpu
 
 TOL64, TOL32 = 1e-12, 1e-5
 
+# Each x-row spans several element blocks of the HIP kernels (a block owns a
+# run of up to 256 / (P+2)^2 consecutive elements of one row) with a ragged
+# last block.
 CASES = [
-    ((5, 3, 2), 1, ob.MODAL),
-    ((3, 2, 3), 2, ob.SDME_H),
-    ((2, 2, 2), 3, ob.SDME_H),      # unit cube of 8 hexahedra, P=3
-    ((3, 2, 2), 4, ob.SDME_M),      # 12 elements: ragged last block
-    ((2, 1, 3), 5, ob.NODAL),
-    ((2, 2, 1), 6, ob.SDME_K),
-    ((1, 3, 1), 7, ob.MODAL),
+    ((31, 2, 2), 1, ob.MODAL),
+    ((18, 2, 1), 2, ob.SDME_H),
+    ((12, 2, 2), 3, ob.SDME_H),
+    ((9, 2, 1), 4, ob.SDME_M),
+    ((7, 1, 2), 5, ob.NODAL),
+    ((5, 2, 1), 6, ob.SDME_K),
+    ((4, 2, 1), 7, ob.MODAL),
     ((3, 1, 1), 8, ob.SDME_H),
 ]
 IDS = ["P%d-%s" % (c[1], ob.KIND_NAMES[c[2]]) for c in CASES]
@@ -33,8 +36,8 @@ IDS = ["P%d-%s" % (c[1], ob.KIND_NAMES[c[2]]) for c in CASES]
 def pair(request):
     n, P, kind = request.param
     mu, lam = inputs.lognormal_lame(100 + P, n[0] * n[1] * n[2], 1.0e3, 0.3)
-    return Pair(n, (1.0, 0.75, 1.25), P, kind=kind, dirichlet=inputs.face_bits(0), mu=mu, lam=lam,
-                rho=1.7)
+    bc = inputs.face_bits(0) | inputs.face_bits(1, comps=(2,)) | inputs.face_bits(3, comps=(0, 1))
+    return Pair(n, (1.0, 0.75, 1.25), P, kind=kind, dirichlet=bc, mu=mu, lam=lam, rho=1.7)
 
 
 def _inputs(p, seed):
