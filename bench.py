@@ -73,12 +73,14 @@ def measured_traffic():
         return None
 
 
-def setup(name):
+def setup(name, kind=None):
     import torch
 
     from paper_2104_13466_amd import inputs
     from paper_2104_13466_amd.sdme import Context
-    w = inputs.WORKLOADS[name]
+    w = dict(inputs.WORKLOADS[name])
+    if kind is not None:
+        w["kind"] = kind
     n, L, P = w["n"], w["L"], w["P"]
     ctx = Context(n, L, P, basis=w["kind"], dirichlet=w["dirichlet"])
     lam0, mu0 = inputs.lame(w["E"], w["nu"])
@@ -188,15 +190,16 @@ def cpu_baseline(w, seconds=10.0):
 
 
 def full_solve(ctx, mat, u0, a):
-    """Newton-PCG time-to-solution in FP64 and mixed: the top displacement is
-    applied in equal increments (load stepping); each increment starts from the
-    previous solution plus the affine increment and runs the damped Newton of
-    sdme_newton_static to 1e-8 with PCG to 1e-8."""
+    """Newton-PCG time-to-solution in FP64 and mixed: the top displacement
+    (a.solve_compression of the height) is applied in equal increments (load
+    stepping); each increment starts from the previous solution plus the
+    affine increment and runs the damped Newton of sdme_newton_static to 1e-8
+    with PCG to 1e-8."""
     import torch
 
     from paper_2104_13466_amd.sdme import FP32, FP64
     G = np.zeros((3, 3))
-    G[2, 2] = -0.2 / a.increments
+    G[2, 2] = -a.solve_compression / a.increments
     inc = torch.tensor(ctx.affine_field([0, 0, 0], G), device="cuda")
     out = {}
     sols = {}
@@ -219,7 +222,238 @@ def full_solve(ctx, mat, u0, a):
     out["max_rel_diff_mixed_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
                                          sols["fp64"].abs().max()).item()
     out["increments"] = a.increments
+    out["compression"] = a.solve_compression
     return out
+
+
+# ------------------------------------------------------------------ cases
+# Further measurements of the hot path on the other workloads; each prints one
+# JSON line of its own (python bench.py --case NAME).
+KIND_NAMES = {0: "nodal", 1: "modal", 2: "sdme_m", 3: "sdme_k", 4: "sdme_h"}
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, 1e3 * (time.perf_counter() - t0)
+
+
+def case_sweep(a):
+    """Polynomial-order sweep at ~2e7 DOF (P = 2, 4, 6, 8, SDME-H): operator
+    launch times and one Newton iteration (PCG to 1e-8) in FP64 and mixed;
+    then the same mixed Newton iteration at P = 4 for every basis kind."""
+    import gc
+
+    import torch
+
+    from paper_2104_13466_amd.sdme import FP32, FP64
+    rows = []
+    for wl in ("compress_p2", "compress_p4", "compress_p6", "compress_p8"):
+        w, ctx, mat, u0 = setup(wl)
+        N = 3 * ctx.Nn
+        row = {"workload": wl, "P": w["P"], "dofs": N, "elements": ctx.E}
+        row["kernel_ms"] = {"%s_%s" % (r[0], r[1]): round(r[2], 4) for r in kernel_table(ctx, mat, u0)}
+        R = torch.zeros(N, dtype=torch.float64, device="cuda")
+        du = torch.zeros_like(R)
+        for prec, name in ((FP64, "fp64"), (FP32, "mixed")):
+            u = u0.clone()
+            st, ms = timed(lambda: newton_iteration(ctx, mat, prec, u, R, du, a.rtol))
+            row[name] = {"ms": round(ms, 1), "pcg_iterations": st["iterations"],
+                         "replacements": st["outer"], "rel_residual": st["rel_residual"]}
+            log("%s %s: %s" % (wl, name, row[name]))
+        row["speedup_mixed_vs_fp64"] = round(row["fp64"]["ms"] / row["mixed"]["ms"], 3)
+        rows.append(row)
+        del ctx, mat, u0, R, du, u
+        gc.collect()
+        torch.cuda.empty_cache()
+    bases = []
+    for kind in (4, 2, 3, 1, 0):
+        w, ctx, mat, u0 = setup("compress_p4", kind=kind)
+        N = 3 * ctx.Nn
+        R = torch.zeros(N, dtype=torch.float64, device="cuda")
+        du = torch.zeros_like(R)
+        u = u0.clone()
+        from paper_2104_13466_amd.sdme import MASK_BC
+
+        def one():
+            ctx.internal_force(mat, FP64, u, R, flags=MASK_BC)
+            ctx.axpby(-1.0, R, 0.0, R)
+            return ctx.jacobi_pcg(mat, FP32, R, du, u_lin=u, rtol=a.rtol, maxit=30000, check=False)
+        st, ms = timed(one)
+        bases.append({"basis": KIND_NAMES[kind], "pcg_iterations": st["iterations"],
+                      "status": st["status"], "ms": round(ms, 1),
+                      "rel_residual": st["rel_residual"]})
+        log("basis %s: %s" % (KIND_NAMES[kind], bases[-1]))
+        del ctx, mat, u0, R, du, u
+        gc.collect()
+        torch.cuda.empty_cache()
+    return {"case": "sweep", "rtol": a.rtol, "rows": rows, "bases_p4_mixed_newton_iteration": bases}
+
+
+def case_newmark(a):
+    """Implicit Newmark (beta = 1/4, gamma = 1/2) on the 16x4x4 cantilever, P = 4:
+    dead tip traction -z on x = 4 ramped linearly to 5.0 over 20 steps of
+    dt = 0.1, Newton to 1e-8 with Jacobi-PCG to 1e-8; SDME-H, SDME-M and the
+    Lagrange-nodal basis, FP64 and mixed."""
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.sdme import FP32, FP64, Context
+    w = inputs.WORKLOADS["cantilever_p4"]
+    runs = []
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    for kind in (4, 2, 0):
+        ctx = Context(w["n"], w["L"], w["P"], basis=kind, dirichlet=w["dirichlet"])
+        mat = Context.material(torch.full((ctx.E,), mu0, dtype=torch.float64, device="cuda"),
+                               torch.full((ctx.E,), lam0, dtype=torch.float64, device="cuda"),
+                               w["rho"])
+        N = 3 * ctx.Nn
+        funit = torch.zeros(N, dtype=torch.float64, device="cuda")
+        ctx.face_traction(1, [0.0, 0.0, -1.0], funit)
+        flags = ctx.dirichlet_flags()
+        sols = {}
+        for prec, name in ((FP64, "fp64"), (FP32, "mixed")):
+            u = torch.zeros(N, dtype=torch.float64, device="cuda")
+            v = torch.zeros_like(u)
+            acc = torch.zeros_like(u)
+            f = torch.zeros_like(u)
+            tot = {"newton": 0, "pcg_iterations": 0, "replacements": 0}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(1, 21):
+                f.copy_(funit * (5.0 * k / 20))
+                st = ctx.newmark_newton_step(mat, prec, u, v, acc, f, 0.1)
+                tot["newton"] += st["newton"]
+                tot["pcg_iterations"] += st["iterations"]
+                tot["replacements"] += st["outer"]
+            torch.cuda.synchronize()
+            tot["seconds"] = round(time.perf_counter() - t0, 3)
+            # tip deflection: z-displacement of the slot at (x = 4, y = 0.5, z = 0.5)
+            Nx, Ny = w["n"][0] * w["P"] + 1, w["n"][1] * w["P"] + 1
+            Nz = w["n"][2] * w["P"] + 1
+            g = ((Nz // 2) * Ny + Ny // 2) * Nx + Nx - 1
+            tot["tip_uz"] = u[2 * ctx.Nn + g].item()
+            sols[name] = u
+            runs.append(dict(basis=KIND_NAMES[kind], precision=name, **tot))
+            log("newmark %s %s: %s" % (KIND_NAMES[kind], name, runs[-1]))
+        runs[-1]["max_rel_diff_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
+                                            sols["fp64"].abs().max()).item()
+        del ctx
+    return {"case": "newmark", "workload": "cantilever_p4: 16x4x4 hexahedra on 4x1x1, P=4, "
+            "clamped x=0, tip traction ramped to 5.0 over 20 steps, dt=0.1",
+            "dofs": 3 * inputs.num_nodes(w["n"], w["P"]), "runs": runs}
+
+
+def case_explicit(a):
+    """Central-difference impact on the 64x64x16 block (4x4x1, P = 3, SDME-M):
+    v0 = -0.05 c_L z onto the rigid plane z = 0 (penalty 10E/h), dt from the
+    power iteration at CFL 0.5, FP32 internal force, FP64 update and mass
+    solve; a.steps_explicit steps with the energy balance checked in FP64."""
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.sdme import FP32, FP64, Context
+    w = inputs.WORKLOADS["impact_p3"]
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    ctx = Context(w["n"], w["L"], w["P"], basis=w["kind"], dirichlet=w["dirichlet"])
+    mat = Context.material(torch.full((ctx.E,), mu0, dtype=torch.float64, device="cuda"),
+                           torch.full((ctx.E,), lam0, dtype=torch.float64, device="cuda"), w["rho"])
+    N = 3 * ctx.Nn
+    h = w["L"][2] / w["n"][2]
+    eps = 10 * w["E"] / h
+    cont = (eps, 0.0)
+    cL = np.sqrt(w["E"] * (1 - w["nu"]) / (w["rho"] * (1 + w["nu"]) * (1 - 2 * w["nu"])))
+    v0 = torch.tensor(ctx.affine_field([0, 0, -0.05 * cL], np.zeros((3, 3))), device="cuda")
+    x0 = torch.tensor(inputs.uniform(w["seed"], N, -1, 1, stream=5), device="cuda")
+    zero = torch.zeros(N, dtype=torch.float64, device="cuda")
+    lmax, ms_l = timed(lambda: ctx.lambda_max(mat, zero, x0, iters=60, contact=cont, mass_rtol=1e-8))
+    dt = 0.5 * 2.0 / np.sqrt(lmax)
+    steps = a.steps_explicit
+    # start step u_1 = u_0 + dt v0 + dt^2/2 a_0 from u_0 = 0
+    u_prev = torch.zeros(N, dtype=torch.float64, device="cuda")
+    u_cur = torch.zeros_like(u_prev)
+    u_next = torch.zeros_like(u_prev)
+    ctx.explicit_step(mat, FP32, None, u_prev, u_cur, dt, v0=v0, contact=cont, mass_rtol=1e-8)
+    energies = []
+    mass_its = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps):
+        st = ctx.explicit_step(mat, FP32, u_prev, u_cur, u_next, dt, contact=cont, mass_rtol=1e-8)
+        mass_its += st["mass_iterations"]
+        if k % max(1, steps // 10) == 0 or k == steps - 1:
+            ke, se, ce = ctx.energies(mat, u_prev, u_cur, u_next, dt, contact=cont)
+            energies.append({"step": k, "kinetic": ke, "strain": se, "contact": ce,
+                             "total": ke + se + ce})
+        u_prev, u_cur, u_next = u_cur, u_next, u_prev
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    e0 = 0.5 * w["rho"] * (0.05 * cL) ** 2 * w["L"][0] * w["L"][1] * w["L"][2]
+    drift = max(abs(e["total"] - e0) for e in energies) / e0
+    return {"case": "explicit", "workload": "impact_p3: 64x64x16 hexahedra on 4x4x1, P=3, SDME-M, "
+            "v0=-0.05 c_L onto a rigid plane, penalty 10E/h, CFL 0.5", "dofs": N,
+            "lambda_max": lmax, "dt": dt, "lambda_max_ms": round(ms_l, 1), "steps": steps,
+            "seconds": round(sec, 3), "ms_per_step": round(1e3 * sec / max(steps - 1, 1), 3),
+            "mass_pcg_iterations_per_step": mass_its / max(steps - 1, 1),
+            "initial_kinetic_energy": e0, "max_rel_energy_deviation": drift,
+            "energies": energies}
+
+
+def case_adjoint(a):
+    """Differentiable explicit run on the 16^3 cube, P = 4, SDME-M: per-element
+    log-normal mu, lam (sigma 0.2), 50 central-difference steps at CFL 0.5,
+    J = 1/2 ||u_K - u*||^2 with u* the rollout of the homogeneous material;
+    forward (checkpoint every 10 steps) and adjoint backward timed; the gradient
+    checked against a central difference (h = 1e-6 relative) along a seeded
+    direction."""
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.adjoint import RolloutSpec, SdmeExplicitRollout, rollout
+    from paper_2104_13466_amd.sdme import Context
+    w = inputs.WORKLOADS["adjoint_p4"]
+    ctx = Context(w["n"], w["L"], w["P"], basis=w["kind"], dirichlet=w["dirichlet"])
+    N = 3 * ctx.Nn
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    mu, lam = inputs.lognormal_lame(w["seed"], ctx.E, w["E"], w["nu"])
+    dev = "cuda"
+    mu_t = torch.tensor(mu, device=dev).requires_grad_(True)
+    lam_t = torch.tensor(lam, device=dev).requires_grad_(True)
+    free = 1.0 - ctx.dirichlet_flags().astype(np.float64)
+    cL = np.sqrt(w["E"] * (1 - w["nu"]) / (w["rho"] * (1 + w["nu"]) * (1 - 2 * w["nu"])))
+    v0 = torch.tensor(free * inputs.uniform(w["seed"], N, -0.01 * cL, 0.01 * cL, stream=6),
+                      device=dev)
+    u0 = torch.zeros(N, dtype=torch.float64, device=dev)
+    x0 = torch.tensor(inputs.uniform(w["seed"], N, -1, 1, stream=5), device=dev)
+    mat = Context.material(mu_t.detach(), lam_t.detach(), w["rho"])
+    lmax = ctx.lambda_max(mat, u0, x0, iters=60, mass_rtol=1e-8)
+    dt = 0.5 * 2.0 / np.sqrt(lmax)
+    steps = 50
+    spec0 = RolloutSpec(ctx, w["rho"], u0, v0, dt, steps, torch.zeros_like(u0), checkpoint=10)
+    _, target, _, _ = rollout(spec0, torch.full((ctx.E,), mu0, dtype=torch.float64, device=dev),
+                              torch.full((ctx.E,), lam0, dtype=torch.float64, device=dev),
+                              keep=False)
+    target = target.clone()
+    spec = RolloutSpec(ctx, w["rho"], u0, v0, dt, steps, target, checkpoint=10)
+    J, ms_f = timed(lambda: SdmeExplicitRollout.apply(mu_t, lam_t, spec))
+    _, ms_b = timed(lambda: J.backward())
+    # central difference along a seeded direction (relative perturbation)
+    d_mu = torch.tensor(inputs.uniform(w["seed"], ctx.E, -1, 1, stream=30), device=dev) * mu_t.detach()
+    d_lam = torch.tensor(inputs.uniform(w["seed"], ctx.E, -1, 1, stream=31), device=dev) * lam_t.detach()
+    h = 1e-6
+    with torch.no_grad():
+        Jp = rollout(spec, mu_t + h * d_mu, lam_t + h * d_lam, keep=False)[0]
+        Jm = rollout(spec, mu_t - h * d_mu, lam_t - h * d_lam, keep=False)[0]
+    fd = (Jp - Jm) / (2 * h)
+    ad = float((mu_t.grad * d_mu).sum() + (lam_t.grad * d_lam).sum())
+    return {"case": "adjoint", "workload": "adjoint_p4: 16^3 hexahedra, P=4, SDME-M, log-normal "
+            "mu, lam (sigma 0.2), 50 steps, checkpoint 10", "dofs": N, "dt": dt,
+            "J": J.item(), "forward_ms": round(ms_f, 1), "backward_ms": round(ms_b, 1),
+            "directional_derivative_adjoint": ad, "directional_derivative_fd": fd,
+            "rel_diff": abs(ad - fd) / abs(fd)}
 
 
 def main():
@@ -230,11 +464,18 @@ def main():
     ap.add_argument("--workload", default="compress_p4")
     ap.add_argument("--solve", action="store_true")
     ap.add_argument("--increments", type=int, default=5)
+    # At 47^3, P = 4 the tangent stops being positive definite beyond about
+    # 16 % nominal compression (PCG meets negative curvature and Newton
+    # stalls near the clamped edges), so the load-stepped solve stops at 15 %.
+    ap.add_argument("--solve-compression", type=float, default=0.15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-table", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only the per-operator launches and a 1 GiB copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint"],
+                    help="print the JSON line of a further measurement instead of the benchmark")
+    ap.add_argument("--steps-explicit", type=int, default=2000)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (slab partition + halo "
@@ -244,6 +485,11 @@ def main():
 
     from paper_2104_13466_amd.sdme import FP32, FP64
 
+    if a.case:
+        fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
+              "adjoint": case_adjoint}[a.case]
+        print(json.dumps(fn(a)), flush=True)
+        return
     log("setup %s" % a.workload)
     w, ctx, mat, u0 = setup(a.workload)
     N = 3 * ctx.Nn

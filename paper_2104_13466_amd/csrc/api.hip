@@ -201,6 +201,8 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
       if (c->prof && hipEventRecord(c->ev[2 * j], st) != hipSuccess) return SDME_EDEVICE;
       if (apply_op<T>(c, mat, op, p, Ap, none, 0, &s->done, st)) return SDME_EDEVICE;
       if (c->prof && hipEventRecord(c->ev[2 * j + 1], st) != hipSuccess) return SDME_EDEVICE;
+      // p^T A p by a separate streaming dot (measured faster than partial sums
+      // fused into the operator kernel)
       if (launch_pcg_pap<T>(p, Ap, s, N, red_at(c, 6), st)) return SDME_EDEVICE;
       if (launch_pcg_update<T>(x, r, p, Ap, d, s, N, red_at(c, 4), st)) return SDME_EDEVICE;
       if (launch_pcg_pupdate<T>(p, r, d, s, N, st)) return SDME_EDEVICE;
@@ -837,7 +839,8 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
   int rc = SDME_OK;
   double shift = dyn ? dyn->b1 : 0.0;
   // Damped Newton: when the updated state inverts an element (det F <= 0),
-  // the last increment is halved (u -= alpha du, alpha halved) up to 20 times.
+  // the last increment is halved (u -= alpha du, alpha halved), up to 20
+  // times per Newton iteration.
   double alpha = 1.0;
   int halvings = 0;
   for (int k = 0;; k++) {
@@ -854,6 +857,7 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
       continue;
     }
     alpha = 1.0;
+    halvings = 0;
     // psi = f - R
     if (f_ext) {
       if (launch_axpbypcz(psi, 1.0, f_ext, 0.0, -1.0, R, N, st)) return SDME_EDEVICE;
@@ -1075,7 +1079,8 @@ extern "C" int sdme_energies(sdme_ctx *c, const sdme_material *mat, const double
   // v = (u_next - u_prev) / (2 dt); KE = 1/2 v^T M v (fused element-local dot)
   if (launch_axpbypcz(w.t1, 0.5 / dt, u_next, 0.0, -0.5 / dt, u_prev, N, st) ||
       launch_fill<double>(w.t2, 0.0, N, st) ||
-      launch_mass<double>(c->P, c->m64, mat->rho, w.t1, w.t2, 0, red_at(c, 12), 1, nullptr, st))
+      launch_mass<double>(c->P, c->m64, mat->rho, w.t1, w.t2, 0, red_at(c, 12), 1, nullptr, st) ||
+      launch_fin2(red_at(c, 12), elem_blocks(c->P, 8, c->d.nx, c->d.ny, c->d.nz), st))
     return SDME_EDEVICE;
   if (hipMemcpyAsync(c->h_res, c->results + 12, sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||

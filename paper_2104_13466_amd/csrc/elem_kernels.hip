@@ -195,28 +195,38 @@ __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, co
 }
 
 // Forward contractions of the three gathered components (tile, synchronised)
-// into X[comp][kind][c].  The xi1 stage of one component overlaps the xi2
-// stage of the previous one through two LDS buffers (one buffer and extra
-// barriers when LDS is short).  Ends after a barrier that follows the last
-// read of the tile.
+// into X[comp][kind][c].  With three LDS buffers the xi1 stages of all
+// components run before one barrier; with two, the xi1 stage of one component
+// overlaps the xi2 stage of the previous one; with one, extra barriers.  Ends
+// after a barrier that follows the last read of the tile.
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void forward_lds(const T *sB, const T *sD, const T *tile, T *st,
                                             const Slab &s, T (&X)[3][3][K::n]) {
-  constexpr int n = K::n, HB = K::SB / 2, CS = n * n * K::TX;
-  constexpr bool single = K::Dm::DBUF == 1;
+  constexpr int n = K::n, SB1 = K::Dm::SB1, CS = n * n * K::TX, NB = K::Dm::DBUF;
   const T *su = tile + s.le * K::Dm::P;
-  T *st1 = single ? st : st + HB;
-  stage1<K, T, GRAD>(sB, sD, su, st, s);
-  __syncthreads();
-  stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
-  if (single) __syncthreads();
-  stage1<K, T, GRAD>(sB, sD, su + CS, st1, s);
-  __syncthreads();
-  stage2<K, T, GRAD>(sB, sD, st1, s, X[1]);
-  if (single) __syncthreads();
-  stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st, s);
-  __syncthreads();
-  stage2<K, T, GRAD>(sB, sD, st, s, X[2]);
+  if constexpr (NB == 3) {
+    stage1<K, T, GRAD>(sB, sD, su, st, s);
+    stage1<K, T, GRAD>(sB, sD, su + CS, st + SB1, s);
+    stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st + 2 * SB1, s);
+    __syncthreads();
+    stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
+    stage2<K, T, GRAD>(sB, sD, st + SB1, s, X[1]);
+    stage2<K, T, GRAD>(sB, sD, st + 2 * SB1, s, X[2]);
+  } else {
+    constexpr bool single = NB == 1;
+    T *st1 = single ? st : st + SB1;
+    stage1<K, T, GRAD>(sB, sD, su, st, s);
+    __syncthreads();
+    stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
+    if (single) __syncthreads();
+    stage1<K, T, GRAD>(sB, sD, su + CS, st1, s);
+    __syncthreads();
+    stage2<K, T, GRAD>(sB, sD, st1, s, X[1]);
+    if (single) __syncthreads();
+    stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st, s);
+    __syncthreads();
+    stage2<K, T, GRAD>(sB, sD, st, s, X[2]);
+  }
 }
 
 // Physical gradient of the field at Gauss point (i1, i2, q3) from X.
@@ -385,7 +395,7 @@ __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
                                               T *sg, T *st, T *tile, const int64_t *s_row,
                                               T *__restrict__ y, bool mask,
                                               const T *__restrict__ vdot, double &dot) {
-  constexpr int HB = (K::Dm::DBUF == 2) ? K::SB / 2 : 0;
+  constexpr int HB = (K::Dm::DBUF >= 2) ? K::Dm::SB1 : 0;
   write_g<K, T, GRAD>(A[0], sg, s);
   __syncthreads();
 #pragma unroll
@@ -413,6 +423,18 @@ __device__ __forceinline__ void zero_acc(T (&A)[3][3][K::n]) {
     for (int k = 0; k < 3; k++)
 #pragma unroll
       for (int c = 0; c < K::n; c++) A[i][k][c] = T(0);
+}
+
+// Block sum of v (all threads call) stored by thread 0 as the block's
+// partial (partials[2 b], partials[2 b + 1] = 0), summed in block order by a
+// one-block kernel launched after the element kernel.
+template <int NT>
+__device__ __forceinline__ void block_partial_t(double v, Reduce red, double *s_red) {
+  double t = block_sum<NT>(v, s_red);
+  if (threadIdx.x == 0) {
+    red.partials[2 * blockIdx.x] = t;
+    red.partials[2 * blockIdx.x + 1] = 0.0;
+  }
 }
 
 // Common kernel prologue: tables, slab coordinates and tile row offsets
@@ -605,8 +627,8 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   }
   if (REC && bad && s.valid) atomicOr(m.flag, 1);
   double dot = 0;
-  transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0, (const T *)nullptr,
-                                   dot);
+  transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0,
+                                   (const T *)nullptr, dot);
 }
 
 // ====================================================================== mass
@@ -637,10 +659,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_mass(MeshK<T> m, T rho, c
   }
   double dot = 0;
   transpose_all<K, T, false, RED>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0, v, dot);
-  if (RED) {
-    double t = block_sum<K::NT>(dot, s_red);
-    grid_reduce_finish<K::NT>(t, red, s_red, gridDim.x);
-  }
+  if (RED) block_partial_t<K::NT>(dot, red, s_red);
 }
 
 // ================================================================= diagonal
@@ -909,21 +928,19 @@ int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, con
                      const int *skip, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
-  (void)red;
-  if (do_red) return -2;  // p^T A p is taken by a separate dot product
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
-  bool mass = msr != T(0);
+  const bool mass = msr != T(0);
+  (void)red;
+  if (do_red) return -2;  // p^T A p is taken by a separate streaming dot product
+#define SDME_TAN(REC, MASS)                                                                 \
+  hipLaunchKernelGGL((k_tangent<P, Q, T, REC, MASS>), grid, block, 0, st, m, mu, lam, ulin, \
+                     state, msr, v, y, mask, skip)
   if (ulin) {
-    if (mass)
-      hipLaunchKernelGGL((k_tangent<P, Q, T, true, true>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
-    else
-      hipLaunchKernelGGL((k_tangent<P, Q, T, true, false>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
+    if (mass) SDME_TAN(true, true); else SDME_TAN(true, false);
   } else {
-    if (mass)
-      hipLaunchKernelGGL((k_tangent<P, Q, T, false, true>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
-    else
-      hipLaunchKernelGGL((k_tangent<P, Q, T, false, false>), grid, block, 0, st, m, mu, lam, ulin, state, msr, v, y, mask, skip);
+    if (mass) SDME_TAN(false, true); else SDME_TAN(false, false);
   }
+#undef SDME_TAN
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

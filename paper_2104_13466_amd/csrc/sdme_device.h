@@ -24,7 +24,9 @@ struct Dims {
   // A block owns NE consecutive elements of one x-row of the mesh.  LDS:
   //  - per element, region A: the xi3-contracted fluxes g1..g3 of one
   //    component (3 n Q^2); region B: DBUF buffers of xi1 partial sums
-  //    (2 n^2 Q each; two buffers let consecutive components overlap);
+  //    (2 n^2 Q each; three buffers let the xi1 stages of the three
+  //    components run before a single barrier, two let consecutive
+  //    components overlap);
   //  - per block, the tile: the block's slots [3][n][n][TX] with
   //    TX = NE P + 1 (input gathered once, then the output accumulated),
   //    and the 64-bit global offsets of its 3 n^2 rows (RW words).
@@ -43,7 +45,15 @@ struct Dims {
     while (ne > 1 && lds_words(ne, dbuf) * WORD > LDS_CAP) ne--;
     return ne;
   }
-  static constexpr int DBUF = (lds_words(1, 2) * WORD <= LDS_CAP) ? 2 : 1;
+  // three buffers (the xi1 stages of all components before one barrier) when
+  // they fit in 80 KiB, else two, else one; at P = 4 two buffers were
+  // measured faster (three: faster at P = 2, 6, 8)
+#ifndef SDME_TRIPLE
+#define SDME_TRIPLE 1
+#endif
+  static constexpr int DBUF = (SDME_TRIPLE && P != 4 && lds_words(NE_T, 3) * WORD <= 81920) ? 3
+                              : (lds_words(1, 2) * WORD <= LDS_CAP)             ? 2
+                                                                                : 1;
   static constexpr int NE = ne_fit(DBUF);
   static constexpr int SB = DBUF * SB1;
   static constexpr int SE = SA + SB;

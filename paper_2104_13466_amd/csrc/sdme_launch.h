@@ -82,6 +82,10 @@ int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n,
 // pAp = p . Ap (skipped when done)
 template <typename T>
 int launch_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n, Reduce red2, hipStream_t st);
+// One-block finishing passes over nb block partials (written by a streaming or
+// element kernel with a reduction): result[0..1], or the solver's p^T A p.
+int launch_fin2(Reduce red2, int nb, hipStream_t st);
+int launch_pcg_pap_fin(PcgDev *s, Reduce red2, int nb, hipStream_t st);
 // residual replacement: r32 = float(r64); rz = r32.(r32/d); beta = rz/rz_old;
 // done = (r64.r64 <= tol2); upd2 = delta^2 r64.r64; then p = r32/d + beta p
 int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,

@@ -228,6 +228,17 @@ __global__ __launch_bounds__(NTV) void k_pcg_pap_fin(PcgDev *s, Reduce red, int 
   sum_partials2(red.partials, nb, a, b, s_red);
   if (threadIdx.x == 0) s->pAp = a;
 }
+// Finishing passes for reductions whose block partials were written by an
+// element kernel of nb blocks.
+int launch_fin2(Reduce red2, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin2, dim3(1), dim3(NTV), 0, st, red2, nb);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+int launch_pcg_pap_fin(PcgDev *s, Reduce red2, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_pap_fin, dim3(1), dim3(NTV), 0, st, s, red2, nb);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <typename T>
 int launch_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n, Reduce red2, hipStream_t st) {
   const int nb = grid_for_u(n);
