@@ -27,12 +27,11 @@ struct EK {
   // shared memory words of a block: row offsets, per-element regions, the
   // tile, tables
   static constexpr int SMEM = RW + NE * SE + TILE + TS;
-  // Gauss-point slabs of stored state kept in flight by the tangent action
-#ifdef SDME_PF
-  static constexpr int PF = SDME_PF;
-#else
-  static constexpr int PF = 1;
-#endif
+  // Stored-state tangent action: PIPE selects two named buffers of
+  // Gauss-point slabs requested ahead (the first two before the forward
+  // contractions); otherwise one slab is prefetched per step.  Chosen by
+  // measurement at ~2e7 DOF per order and precision.
+  static constexpr bool PIPE = sizeof(T) == 4 ? (P >= 4 && P <= 6) : (P <= 2);
 };
 
 // Thread/element coordinates inside a block.  Block b owns the run of NE
@@ -523,18 +522,14 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   using K = EK<P, Q, T>;
   if (skip && *skip) return;
   SDME_SETUP
-  // stored state: the first PD Gauss-point slabs are requested before the
-  // gather so that their latency hides behind the forward contractions; the
-  // loop keeps PD slabs in flight
   constexpr int QQQ = Q * Q * Q;
-  constexpr int PD = REC ? 1 : (Q < K::PF ? Q : K::PF);
+  constexpr bool PIPE = !REC && K::PIPE;
   const T *__restrict__ sp = state + (size_t)(s.valid ? s.e : 0) * 10 * QQQ + s.t2;
-  T Gb[PD][10];
-  if (!REC) {
+  // one-slab prefetch: the first slab is requested before the gather
+  T Gn[10];
+  if (!REC && !PIPE) {
 #pragma unroll
-    for (int d = 0; d < PD; d++)
-#pragma unroll
-      for (int k = 0; k < 10; k++) Gb[d][k] = sp[k * QQQ + d * K::QQ];
+    for (int k = 0; k < 10; k++) Gn[k] = sp[k * QQQ];
   }
   const T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
   SDME_GATHER((REC ? ulin : v), (REC ? false : mask != 0))
@@ -545,48 +540,36 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     gather_tile<K>(m, s, s_row, v, mask != 0, tile);
     __syncthreads();
   }
+  // two named buffers: the first two slabs are requested once the gather has
+  // completed (memory waits are in order, so earlier requests would be
+  // waited for by the gather) and stay in flight through the forward
+  // contractions, which wait only on LDS; the empty asm keeps the compiler
+  // from moving the loads down to their first use.
+  T Ga[10], Gc[10];
+  if (PIPE) {
+#pragma unroll
+    for (int k = 0; k < 10; k++) Ga[k] = sp[k * QQQ];
+    __builtin_amdgcn_sched_barrier(0);
+    const int o1 = min(1, Q - 1) * K::QQ;
+#pragma unroll
+    for (int k = 0; k < 10; k++) Gc[k] = sp[k * QQQ + o1];
+    asm volatile("" ::: "memory");
+  }
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   zero_tile<K>(tile);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   zero_acc<K>(A);
-  bool bad = false;
-#pragma unroll 1
-  for (int q3 = 0; q3 < Q; q3++) {
-    T dF[9], G[9], c1;
-    if (REC) {
-      T H[9];
-      grad_at<K, T>(m, s_tab, q3, XU, H);
-      Kin<T> kk;
-      if (!kinematics(H, kk)) {
-        bad = true;
-        kk.lnJ = T(0);
-#pragma unroll
-        for (int i = 0; i < 9; i++) kk.G[i] = T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < 9; i++) G[i] = kk.G[i];
-      c1 = mue - lae * kk.lnJ;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 9; k++) G[k] = Gb[0][k];
-      c1 = Gb[0][9];
-#pragma unroll
-      for (int d = 0; d + 1 < PD; d++)
-#pragma unroll
-        for (int k = 0; k < 10; k++) Gb[d][k] = Gb[d + 1][k];
-      if (q3 + PD < Q) {
-#pragma unroll
-        for (int k = 0; k < 10; k++) Gb[PD - 1][k] = sp[k * QQQ + (q3 + PD) * K::QQ];
-      }
-    }
+  // linearised stress at Gauss point (i1, i2, q3) from G = F^-1, c1:
+  // dP = mu dF + c1 (G dF G)^T + lam tr(G dF) G^T, one row at a time,
+  // accumulated at once into the transposed xi3 contraction (few live
+  // temporaries)
+  auto point = [&](int q3, const T *G, T c1) {
+    T dF[9];
     grad_at<K, T>(m, s_tab, q3, X, dF);
     T val[3];
     if (MASS) value_at<K, T>(s_tab, q3, X, val);
-    // dP = mu dF + c1 (G dF G)^T + lam tr(G dF) G^T, one row at a time,
-    // accumulated at once into the transposed xi3 contraction (few live
-    // temporaries)
     T Am[9];
 #pragma unroll
     for (int I = 0; I < 3; I++)
@@ -623,6 +606,57 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
         A[i][0][c] += dq[c] * fr[2];
         if (MASS) A[i][0][c] += bq[c] * mv;
       }
+    }
+  };
+  bool bad = false;
+  if (REC) {
+#pragma unroll 1
+    for (int q3 = 0; q3 < Q; q3++) {
+      T H[9];
+      grad_at<K, T>(m, s_tab, q3, XU, H);
+      Kin<T> kk;
+      if (!kinematics(H, kk)) {
+        bad = true;
+        kk.lnJ = T(0);
+#pragma unroll
+        for (int i = 0; i < 9; i++) kk.G[i] = T(0);
+      }
+      point(q3, kk.G, mue - lae * kk.lnJ);
+    }
+  } else if (PIPE) {
+    // Gauss-point slabs in pairs with the two named buffers (no register
+    // rotation): slab q3 + 2 is requested into a buffer as soon as slab q3
+    // has used it, and each wait leaves the other buffer's requests
+    // outstanding.  The last requests repeat the last slab so that every
+    // request is unconditional; the scheduling barriers keep each request
+    // after the computation that frees its buffer.
+#pragma unroll 1
+    for (int q3 = 0; q3 < Q; q3 += 2) {
+      point(q3, Ga, Ga[9]);
+      __builtin_amdgcn_sched_barrier(0);
+      const int oa = min(q3 + 2, Q - 1) * K::QQ;
+#pragma unroll
+      for (int k = 0; k < 10; k++) Ga[k] = sp[k * QQQ + oa];
+      if (Q % 2 == 0 || q3 + 1 < Q) {
+        point(q3 + 1, Gc, Gc[9]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int oc = min(q3 + 3, Q - 1) * K::QQ;
+#pragma unroll
+        for (int k = 0; k < 10; k++) Gc[k] = sp[k * QQQ + oc];
+      }
+    }
+  } else {
+    // one slab prefetched while the current one is processed
+#pragma unroll 1
+    for (int q3 = 0; q3 < Q; q3++) {
+      T G[10];
+#pragma unroll
+      for (int k = 0; k < 10; k++) G[k] = Gn[k];
+      if (q3 + 1 < Q) {
+#pragma unroll
+        for (int k = 0; k < 10; k++) Gn[k] = sp[k * QQQ + (q3 + 1) * K::QQ];
+      }
+      point(q3, G, G[9]);
     }
   }
   if (REC && bad && s.valid) atomicOr(m.flag, 1);
