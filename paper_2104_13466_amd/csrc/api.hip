@@ -1080,7 +1080,7 @@ extern "C" int sdme_energies(sdme_ctx *c, const sdme_material *mat, const double
   if (launch_axpbypcz(w.t1, 0.5 / dt, u_next, 0.0, -0.5 / dt, u_prev, N, st) ||
       launch_fill<double>(w.t2, 0.0, N, st) ||
       launch_mass<double>(c->P, c->m64, mat->rho, w.t1, w.t2, 0, red_at(c, 12), 1, nullptr, st) ||
-      launch_fin2(red_at(c, 12), elem_blocks(c->P, 8, c->d.nx, c->d.ny, c->d.nz), st))
+      launch_fin2(red_at(c, 12), elem_blocks(c->P, 8, c->d.nx, c->d.ny, c->d.nz, false), st))
     return SDME_EDEVICE;
   if (hipMemcpyAsync(c->h_res, c->results + 12, sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||

@@ -18,9 +18,9 @@
 
 namespace sdme {
 
-template <int P, int Q, typename T>
+template <int P, int Q, typename T, bool GRAD = true>
 struct EK {
-  using Dm = Dims<P, Q, (int)sizeof(T)>;
+  using Dm = Dims<P, Q, (int)sizeof(T), GRAD>;
   static constexpr int n = Dm::n, n3 = Dm::n3, QQ = Dm::QQ, NE = Dm::NE, NT = Dm::NT;
   static constexpr int SA = Dm::SA, SB = Dm::SB, SE = Dm::SE, TS = Dm::TSIZE;
   static constexpr int TX = Dm::TX, TILE = Dm::TILE, ROWS = Dm::ROWS, RW = Dm::RW;
@@ -30,8 +30,8 @@ struct EK {
   // Stored-state tangent action: PIPE selects two named buffers of
   // Gauss-point slabs requested ahead (the first two before the forward
   // contractions); otherwise one slab is prefetched per step.  Chosen by
-  // measurement at ~2e7 DOF per order and precision.
-  static constexpr bool PIPE = sizeof(T) == 4 ? (P >= 4 && P <= 6) : (P <= 2);
+  // measurement at ~2e7 DOF per order and precision (FP32, P = 4..6).
+  static constexpr bool PIPE = sizeof(T) == 4 && P >= 4 && P <= 6;
 };
 
 // Thread/element coordinates inside a block.  Block b owns the run of NE
@@ -133,12 +133,20 @@ __device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, co
   }
 }
 
-// xi1 contraction of one component: st0[c][b][q1] = sum_a B[q1][a] u[c][b][a],
-// st1 with D; su points at the element's first slot in the tile (rows of
-// stride TX).
+// Contiguous, 16-byte aligned LDS row of N values (wide LDS loads).
+template <int N, typename T>
+__device__ __forceinline__ void lds_row(const T *p, T (&r)[N]) {
+  const T *a = (const T *)__builtin_assume_aligned(p, 16);
+#pragma unroll
+  for (int k = 0; k < N; k++) r[k] = a[k];
+}
+
+// xi1 contraction of one component: st[0][c][q1][b] = sum_a B[q1][a]
+// u[c][b][a], st[1][c][q1][b] with D (rows of NP); su points at the element's
+// first slot in the tile (rows of stride TX).
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T *st, const Slab &s) {
-  constexpr int n = K::n, Q = K::Dm::Q, TX = K::TX;
+  constexpr int n = K::n, Q = K::Dm::Q, TX = K::TX, NP = K::Dm::NP;
   if (s.i2 < n) {
     T rb[n], rd[n];
 #pragma unroll
@@ -155,8 +163,8 @@ __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T 
         sb += rb[a] * x;
         if (GRAD) sd += rd[a] * x;
       }
-      st[(c * n + s.i2) * Q + s.i1] = sb;
-      if (GRAD) st[n * n * Q + (c * n + s.i2) * Q + s.i1] = sd;
+      st[(c * Q + s.i1) * NP + s.i2] = sb;
+      if (GRAD) st[((n + c) * Q + s.i1) * NP + s.i2] = sd;
     }
   }
 }
@@ -166,7 +174,7 @@ __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T 
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, const Slab &s,
                                        T (&X)[3][K::n]) {
-  constexpr int n = K::n, Q = K::Dm::Q;
+  constexpr int n = K::n, Q = K::Dm::Q, NP = K::Dm::NP;
   T rb[n], rd[n];
 #pragma unroll
   for (int b = 0; b < n; b++) {
@@ -175,14 +183,16 @@ __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, co
   }
 #pragma unroll
   for (int c = 0; c < n; c++) {
+    T t0[n], t1[n];
+    lds_row<n>(st + (c * Q + s.i1) * NP, t0);
+    if (GRAD) lds_row<n>(st + ((n + c) * Q + s.i1) * NP, t1);
     T bb = T(0), bd = T(0), db = T(0);
 #pragma unroll
     for (int b = 0; b < n; b++) {
-      T t0 = st[(c * n + b) * Q + s.i1];
-      bb += rb[b] * t0;
+      bb += rb[b] * t0[b];
       if (GRAD) {
-        bd += rd[b] * t0;
-        db += rb[b] * st[n * n * Q + (c * n + b) * Q + s.i1];
+        bd += rd[b] * t0[b];
+        db += rb[b] * t1[b];
       }
     }
     X[0][c] = bb;
@@ -291,26 +301,26 @@ __device__ __forceinline__ void accum_at(const T *tab, int q3, const T f[9], con
 }
 
 // Store the xi3-contracted fluxes of one component (kinds 0 BB-type, 1 BD,
-// 2 DB) into sg[kind][c][q2][q1].
+// 2 DB) into sg[kind][c][q1][q2] (rows of QP).
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void write_g(const T (&A)[3][K::n], T *sg, const Slab &s) {
-  constexpr int n = K::n, Q = K::Dm::Q, QQ = K::QQ;
+  constexpr int n = K::n, Q = K::Dm::Q, QP = K::Dm::QP;
 #pragma unroll
   for (int c = 0; c < n; c++) {
-    sg[(c * Q + s.i2) * Q + s.i1] = A[0][c];
+    sg[(c * Q + s.i1) * QP + s.i2] = A[0][c];
     if (GRAD) {
-      sg[n * QQ + (c * Q + s.i2) * Q + s.i1] = A[1][c];
-      sg[2 * n * QQ + (c * Q + s.i2) * Q + s.i1] = A[2][c];
+      sg[((n + c) * Q + s.i1) * QP + s.i2] = A[1][c];
+      sg[((2 * n + c) * Q + s.i1) * QP + s.i2] = A[2][c];
     }
   }
 }
 
-// Transposed xi2 contraction: thread (q1 = i1, b = i2) -> st[c][b][q1] (B in
-// xi1) and st[n^2 Q + ...] (D in xi1).
+// Transposed xi2 contraction: thread (q1 = i1, b = i2) -> st[0][c][b][q1]
+// (B in xi1) and st[1][c][b][q1] (D in xi1), rows of QP.
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage2t(const T *sB, const T *sD, const T *sg, T *st,
                                         const Slab &s) {
-  constexpr int n = K::n, Q = K::Dm::Q, QQ = K::QQ;
+  constexpr int n = K::n, Q = K::Dm::Q, QP = K::Dm::QP;
   if (s.i2 < n) {
     T cb[Q], cd[Q];
 #pragma unroll
@@ -320,17 +330,23 @@ __device__ __forceinline__ void stage2t(const T *sB, const T *sD, const T *sg, T
     }
 #pragma unroll
     for (int c = 0; c < n; c++) {
+      T g0[Q], g1[Q], g2[Q];
+      lds_row<Q>(sg + (c * Q + s.i1) * QP, g0);
+      if (GRAD) {
+        lds_row<Q>(sg + ((n + c) * Q + s.i1) * QP, g1);
+        lds_row<Q>(sg + ((2 * n + c) * Q + s.i1) * QP, g2);
+      }
       T hb = T(0), hd = T(0);
 #pragma unroll
       for (int q = 0; q < Q; q++) {
-        hb += cb[q] * sg[(c * Q + q) * Q + s.i1];
+        hb += cb[q] * g0[q];
         if (GRAD) {
-          hb += cd[q] * sg[n * QQ + (c * Q + q) * Q + s.i1];
-          hd += cb[q] * sg[2 * n * QQ + (c * Q + q) * Q + s.i1];
+          hb += cd[q] * g1[q];
+          hd += cb[q] * g2[q];
         }
       }
-      st[(c * n + s.i2) * Q + s.i1] = hb;
-      if (GRAD) st[n * n * Q + (c * n + s.i2) * Q + s.i1] = hd;
+      st[(c * n + s.i2) * QP + s.i1] = hb;
+      if (GRAD) st[((n + c) * n + s.i2) * QP + s.i1] = hd;
     }
   }
 }
@@ -341,7 +357,7 @@ __device__ __forceinline__ void stage2t(const T *sB, const T *sD, const T *sg, T
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *sB, const T *sD,
                                              const T *st, T *tile) {
-  constexpr int n = K::n, Q = K::Dm::Q, P = K::Dm::P, TX = K::TX;
+  constexpr int n = K::n, Q = K::Dm::Q, P = K::Dm::P, TX = K::TX, QP = K::Dm::QP;
   if (s.valid && s.i1 < n && s.i2 < n) {
     T cb[Q], cd[Q];
 #pragma unroll
@@ -352,11 +368,14 @@ __device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *s
     T *row = tile + ((comp * n) * n + s.i2) * TX + s.le * P + s.i1;
 #pragma unroll
     for (int c = 0; c < n; c++) {
+      T h0[Q], h1[Q];
+      lds_row<Q>(st + (c * n + s.i2) * QP, h0);
+      if (GRAD) lds_row<Q>(st + ((n + c) * n + s.i2) * QP, h1);
       T val = T(0);
 #pragma unroll
       for (int q = 0; q < Q; q++) {
-        val += cb[q] * st[(c * n + s.i2) * Q + q];
-        if (GRAD) val += cd[q] * st[n * n * Q + (c * n + s.i2) * Q + q];
+        val += cb[q] * h0[q];
+        if (GRAD) val += cd[q] * h1[q];
       }
       atomicAdd(row + c * n * TX, val);
     }
@@ -669,10 +688,12 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
 // y = rho M v; RED additionally accumulates v^T M v (sum of element-local
 // products) into red.
 template <int P, int Q, typename T, bool RED>
-__global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_mass(MeshK<T> m, T rho, const T *__restrict__ v,
-                                                          T *__restrict__ y, int mask, Reduce red,
-                                                          const int *__restrict__ skip) {
-  using K = EK<P, Q, T>;
+__global__ __launch_bounds__((EK<P, Q, T, false>::NT)) void k_mass(MeshK<T> m, T rho,
+                                                                 const T *__restrict__ v,
+                                                                 T *__restrict__ y, int mask,
+                                                                 Reduce red,
+                                                                 const int *__restrict__ skip) {
+  using K = EK<P, Q, T, false>;
   if (skip && *skip) return;
   __shared__ double s_red[(K::NT + 63) / 64];
   SDME_PROLOGUE(v, mask != 0)
@@ -982,7 +1003,7 @@ template <int P, typename T>
 int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
                   const int *skip, hipStream_t st) {
   constexpr int Q = P + 2;
-  using K = EK<P, Q, T>;
+  using K = EK<P, Q, T, false>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   if (do_red)
     hipLaunchKernelGGL((k_mass<P, Q, T, true>), grid, block, 0, st, m, rho, v, y, mask, red, skip);

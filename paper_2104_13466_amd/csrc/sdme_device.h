@@ -12,7 +12,9 @@
 
 namespace sdme {
 
-template <int P_, int Q_, int WORD>
+// GRAD = false sizes the LDS regions for value-only contractions (the mass
+// action: B tables only, one kind per stage).
+template <int P_, int Q_, int WORD, bool GRAD = true>
 struct Dims {
   static constexpr int P = P_, Q = Q_, n = P_ + 1;
   static constexpr int n3 = n * n * n;
@@ -23,18 +25,25 @@ struct Dims {
                        TWF = TBF + n * n, TSIZE = TWF + n;
   // A block owns NE consecutive elements of one x-row of the mesh.  LDS:
   //  - per element, region A: the xi3-contracted fluxes g1..g3 of one
-  //    component (3 n Q^2); region B: DBUF buffers of xi1 partial sums
-  //    (2 n^2 Q each; three buffers let the xi1 stages of the three
-  //    components run before a single barrier, two let consecutive
-  //    components overlap);
+  //    component, [kind][c][q1][QP] with q2 fastest; region B: DBUF buffers
+  //    of xi1 partial sums, [kind][c][q1][NP] with b fastest (forward) or
+  //    [kind][c][b][QP] with q1 fastest (transposed).  Every row a thread
+  //    reads is contiguous and 16-byte aligned (row lengths padded to
+  //    multiples of VW words) so that it is read with wide LDS loads.  Three
+  //    buffers let the xi1 stages of the three components run before a
+  //    single barrier, two let consecutive components overlap;
   //  - per block, the tile: the block's slots [3][n][n][TX] with
   //    TX = NE P + 1 (input gathered once, then the output accumulated),
   //    and the 64-bit global offsets of its 3 n^2 rows (RW words).
-  static constexpr int SA = 3 * n * QQ;
-  static constexpr int SB1 = 2 * n * n * Q;
+  static constexpr int VW = 16 / WORD;
+  static constexpr int rup(int x) { return (x + VW - 1) / VW * VW; }
+  static constexpr int NP = rup(n), QP = rup(Q);
+  static constexpr int KA = GRAD ? 3 : 1, KB = GRAD ? 2 : 1;
+  static constexpr int SA = KA * n * Q * QP;
+  static constexpr int SB1 = (KB * n * Q * NP > KB * n * n * QP) ? KB * n * Q * NP : KB * n * n * QP;
   static constexpr int NE_T = (256 / QQ) > 0 ? (256 / QQ) : 1;
   static constexpr int ROWS = 3 * n * n;
-  static constexpr int RW = ROWS * 8 / WORD;
+  static constexpr int RW = rup(ROWS * 8 / WORD);
   // at most 96 KiB of LDS per block (gfx950 has 160 KiB per CU)
   static constexpr int LDS_CAP = 98304;
   static constexpr int lds_words(int ne, int dbuf) {
