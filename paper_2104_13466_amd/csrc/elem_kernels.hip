@@ -24,9 +24,15 @@ struct EK {
   static constexpr int n = Dm::n, n3 = Dm::n3, QQ = Dm::QQ, NE = Dm::NE, NT = Dm::NT;
   static constexpr int SA = Dm::SA, SB = Dm::SB, SE = Dm::SE, TS = Dm::TSIZE;
   static constexpr int TX = Dm::TX, TILE = Dm::TILE, ROWS = Dm::ROWS, RW = Dm::RW;
+  static constexpr int NP = Dm::NP, QP = Dm::QP, TILEP = Dm::rup(TILE);
+  // basis tables as the contraction stages read them from LDS (rows padded
+  // and aligned for wide loads): B, D as [Q][NP]; their transposes Bt, Dt as
+  // [n][QP]; the weights W[Q]
+  static constexpr int LB = 0, LD = Dm::Q * NP, LBT = 2 * Dm::Q * NP, LDT = LBT + n * QP,
+                       LW = LDT + n * QP, TSX = LW + Dm::Q;
   // shared memory words of a block: row offsets, per-element regions, the
   // tile, tables
-  static constexpr int SMEM = RW + NE * SE + TILE + TS;
+  static constexpr int SMEM = RW + NE * SE + TILEP + TSX;
   // Stored-state tangent action: PIPE selects two named buffers of
   // Gauss-point slabs requested ahead (the first two before the forward
   // contractions); otherwise one slab is prefetched per step.  Chosen by
@@ -77,6 +83,26 @@ __host__ __device__ constexpr int blocks_for(int nx, int ny, int nz) {
 template <class K, typename T>
 __device__ __forceinline__ void load_tables(const MeshK<T> &m, T *s_tab) {
   for (int i = threadIdx.x; i < K::TS; i += K::NT) s_tab[i] = m.tab[i];
+}
+
+// The stage tables of EK (LB .. TSX) from the mesh tables (B, D as [Q][n]).
+template <class K, typename T>
+__device__ __forceinline__ void load_stage_tables(const MeshK<T> &m, T *s_tab) {
+  constexpr int n = K::n, Q = K::Dm::Q, NP = K::NP, QP = K::QP;
+  using Dm = typename K::Dm;
+  for (int i = threadIdx.x; i < K::TSX; i += K::NT) {
+    T v = T(0);
+    if (i < K::LBT) {  // B, D rows
+      int t = i / (Q * NP), r = i % (Q * NP), q = r / NP, c = r % NP;
+      if (c < n) v = m.tab[(t ? Dm::TD : Dm::TB) + q * n + c];
+    } else if (i < K::LW) {  // Bt, Dt rows
+      int j = i - K::LBT, t = j / (n * QP), r = j % (n * QP), a = r / QP, q = r % QP;
+      if (q < Q) v = m.tab[(t ? Dm::TD : Dm::TB) + q * n + a];
+    } else {
+      v = m.tab[Dm::TW + (i - K::LW)];
+    }
+    s_tab[i] = v;
+  }
 }
 
 // Global offsets of the rows of the block's tile: row r = (comp n + c) n + b
@@ -149,11 +175,8 @@ __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T 
   constexpr int n = K::n, Q = K::Dm::Q, TX = K::TX, NP = K::Dm::NP;
   if (s.i2 < n) {
     T rb[n], rd[n];
-#pragma unroll
-    for (int a = 0; a < n; a++) {
-      rb[a] = sB[s.i1 * n + a];
-      if (GRAD) rd[a] = sD[s.i1 * n + a];
-    }
+    lds_row<n>(sB + s.i1 * NP, rb);
+    if (GRAD) lds_row<n>(sD + s.i1 * NP, rd);
 #pragma unroll
     for (int c = 0; c < n; c++) {
       T sb = T(0), sd = T(0);
@@ -176,11 +199,8 @@ __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, co
                                        T (&X)[3][K::n]) {
   constexpr int n = K::n, Q = K::Dm::Q, NP = K::Dm::NP;
   T rb[n], rd[n];
-#pragma unroll
-  for (int b = 0; b < n; b++) {
-    rb[b] = sB[s.i2 * n + b];
-    if (GRAD) rd[b] = sD[s.i2 * n + b];
-  }
+  lds_row<n>(sB + s.i2 * NP, rb);
+  if (GRAD) lds_row<n>(sD + s.i2 * NP, rd);
 #pragma unroll
   for (int c = 0; c < n; c++) {
     T t0[n], t1[n];
@@ -238,18 +258,15 @@ __device__ __forceinline__ void forward_lds(const T *sB, const T *sD, const T *t
   }
 }
 
-// Physical gradient of the field at Gauss point (i1, i2, q3) from X.
+// Physical gradient of the field at Gauss point (i1, i2, q3) from X (tab:
+// the stage tables of EK).
 template <class K, typename T>
 __device__ __forceinline__ void grad_at(const MeshK<T> &m, const T *tab, int q3,
                                         const T (&X)[3][3][K::n], T H[9]) {
   constexpr int n = K::n;
-  using Dm = typename K::Dm;
   T bq[n], dq[n];
-#pragma unroll
-  for (int c = 0; c < n; c++) {
-    bq[c] = tab[Dm::TB + q3 * n + c];
-    dq[c] = tab[Dm::TD + q3 * n + c];
-  }
+  lds_row<n>(tab + K::LB + q3 * K::NP, bq);
+  lds_row<n>(tab + K::LD + q3 * K::NP, dq);
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T g0 = T(0), g1 = T(0), g2 = T(0);
@@ -268,12 +285,13 @@ __device__ __forceinline__ void grad_at(const MeshK<T> &m, const T *tab, int q3,
 template <class K, typename T>
 __device__ __forceinline__ void value_at(const T *tab, int q3, const T (&X)[3][3][K::n], T val[3]) {
   constexpr int n = K::n;
-  using Dm = typename K::Dm;
+  T bq[n];
+  lds_row<n>(tab + K::LB + q3 * K::NP, bq);
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T g = T(0);
 #pragma unroll
-    for (int c = 0; c < n; c++) g += tab[Dm::TB + q3 * n + c] * X[i][0][c];
+    for (int c = 0; c < n; c++) g += bq[c] * X[i][0][c];
     val[i] = g;
   }
 }
@@ -284,18 +302,19 @@ template <class K, typename T, bool GRAD, bool VAL>
 __device__ __forceinline__ void accum_at(const T *tab, int q3, const T f[9], const T mv[3],
                                          T (&A)[3][3][K::n]) {
   constexpr int n = K::n;
-  using Dm = typename K::Dm;
+  T bq[n], dq[n];
+  lds_row<n>(tab + K::LB + q3 * K::NP, bq);
+  if (GRAD) lds_row<n>(tab + K::LD + q3 * K::NP, dq);
 #pragma unroll
   for (int c = 0; c < n; c++) {
-    T bq = tab[Dm::TB + q3 * n + c], dq = tab[Dm::TD + q3 * n + c];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       if (GRAD) {
-        A[i][2][c] += bq * f[i * 3 + 0];
-        A[i][1][c] += bq * f[i * 3 + 1];
-        A[i][0][c] += dq * f[i * 3 + 2];
+        A[i][2][c] += bq[c] * f[i * 3 + 0];
+        A[i][1][c] += bq[c] * f[i * 3 + 1];
+        A[i][0][c] += dq[c] * f[i * 3 + 2];
       }
-      if (VAL) A[i][0][c] += bq * mv[i];
+      if (VAL) A[i][0][c] += bq[c] * mv[i];
     }
   }
 }
@@ -323,11 +342,8 @@ __device__ __forceinline__ void stage2t(const T *sB, const T *sD, const T *sg, T
   constexpr int n = K::n, Q = K::Dm::Q, QP = K::Dm::QP;
   if (s.i2 < n) {
     T cb[Q], cd[Q];
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-      cb[q] = sB[q * n + s.i2];
-      if (GRAD) cd[q] = sD[q * n + s.i2];
-    }
+    lds_row<Q>(sB + s.i2 * QP, cb);
+    if (GRAD) lds_row<Q>(sD + s.i2 * QP, cd);
 #pragma unroll
     for (int c = 0; c < n; c++) {
       T g0[Q], g1[Q], g2[Q];
@@ -360,11 +376,8 @@ __device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *s
   constexpr int n = K::n, Q = K::Dm::Q, P = K::Dm::P, TX = K::TX, QP = K::Dm::QP;
   if (s.valid && s.i1 < n && s.i2 < n) {
     T cb[Q], cd[Q];
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-      cb[q] = sB[q * n + s.i1];
-      if (GRAD) cd[q] = sD[q * n + s.i1];
-    }
+    lds_row<Q>(sB + s.i1 * QP, cb);
+    if (GRAD) lds_row<Q>(sD + s.i1 * QP, cd);
     T *row = tile + ((comp * n) * n + s.i2) * TX + s.le * P + s.i1;
 #pragma unroll
     for (int c = 0; c < n; c++) {
@@ -461,12 +474,13 @@ __device__ __forceinline__ void block_partial_t(double v, Reduce red, double *s_
 #define SDME_SETUP                                                              \
   __shared__ __align__(16) T smem[K::SMEM];                                     \
   int64_t *s_row = (int64_t *)smem;                                             \
-  T *tile = smem + K::RW + K::NE * K::SE, *s_tab = tile + K::TILE;              \
-  load_tables<K>(m, s_tab);                                                     \
+  T *tile = smem + K::RW + K::NE * K::SE, *s_tab = tile + K::TILEP;             \
+  load_stage_tables<K>(m, s_tab);                                               \
   Slab s = make_slab<K>(m);                                                     \
   tile_rows<K>(m, s, s_row);                                                    \
   T *su = smem + K::RW + s.le * K::SE, *st = su + K::SA;                        \
-  const T *sB = s_tab + K::Dm::TB, *sD = s_tab + K::Dm::TD, *sW = s_tab + K::Dm::TW; \
+  const T *sB = s_tab + K::LB, *sD = s_tab + K::LD, *sW = s_tab + K::LW;       \
+  const T *sBt = s_tab + K::LBT, *sDt = s_tab + K::LDT;                         \
   __syncthreads();
 #define SDME_GATHER(FIELD, MASK)                                                \
   gather_tile<K>(m, s, s_row, FIELD, MASK, tile);                               \
@@ -512,7 +526,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
     if (OUT) {
       T Pk[9], f[9], mv[3] = {T(0), T(0), T(0)};
       first_pk(H, kk, mue, lae, Pk);
-      T wq = w12 * s_tab[K::Dm::TW + q3];
+      T wq = w12 * sW[q3];
       if (!ok) wq = T(0);
 #pragma unroll
       for (int i = 0; i < 3; i++)
@@ -524,7 +538,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
   if (bad && s.valid) atomicOr(m.flag, 1);
   if (OUT) {
     double dummy = 0;
-    transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, s_row, R, mask != 0, (const T *)nullptr,
+    transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_row, R, mask != 0, (const T *)nullptr,
                                      dummy);
   }
 }
@@ -597,14 +611,11 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
         Am[I * 3 + L] = G[I * 3 + 0] * dF[0 * 3 + L] + G[I * 3 + 1] * dF[1 * 3 + L] +
                         G[I * 3 + 2] * dF[2 * 3 + L];
     const T trl = lae * (Am[0] + Am[4] + Am[8]);
-    const T wq = w12 * s_tab[K::Dm::TW + q3];
+    const T wq = w12 * sW[q3];
     const T s0 = wq * m.ih[0], s1 = wq * m.ih[1], s2 = wq * m.ih[2];
     T bq[K::n], dq[K::n];
-#pragma unroll
-    for (int c = 0; c < K::n; c++) {
-      bq[c] = s_tab[K::Dm::TB + q3 * K::n + c];
-      dq[c] = s_tab[K::Dm::TD + q3 * K::n + c];
-    }
+    lds_row<K::n>(sB + q3 * K::NP, bq);
+    lds_row<K::n>(sD + q3 * K::NP, dq);
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       T fr[3];
@@ -680,7 +691,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   }
   if (REC && bad && s.valid) atomicOr(m.flag, 1);
   double dot = 0;
-  transpose_all<K, T, true, false>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0,
+  transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_row, y, mask != 0,
                                    (const T *)nullptr, dot);
 }
 
@@ -707,13 +718,13 @@ __global__ __launch_bounds__((EK<P, Q, T, false>::NT)) void k_mass(MeshK<T> m, T
   for (int q3 = 0; q3 < Q; q3++) {
     T val[3], mv[3], f[9];
     value_at<K, T>(s_tab, q3, X, val);
-    T wq = w12 * s_tab[K::Dm::TW + q3];
+    T wq = w12 * sW[q3];
 #pragma unroll
     for (int i = 0; i < 3; i++) mv[i] = wq * val[i];
     accum_at<K, T, false, true>(s_tab, q3, f, mv, A);
   }
   double dot = 0;
-  transpose_all<K, T, false, RED>(m, s, A, sB, sD, su, st, tile, s_row, y, mask != 0, v, dot);
+  transpose_all<K, T, false, RED>(m, s, A, sBt, sDt, su, st, tile, s_row, y, mask != 0, v, dot);
   if (RED) block_partial_t<K::NT>(dot, red, s_red);
 }
 
@@ -888,7 +899,7 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_energy(MeshK<double>
       for (int k = 0; k < 9; k++) hh += H[k] * H[k];
       T trH = H[0] + H[4] + H[8];
       T psi = 0.5 * mue * (2.0 * trH + hh) - mue * kk.lnJ + 0.5 * lae * kk.lnJ * kk.lnJ;
-      acc += w12 * s_tab[K::Dm::TW + q3] * psi;
+      acc += w12 * sW[q3] * psi;
     }
   }
   if (!s.valid) acc = 0;
@@ -923,7 +934,7 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_matgrad(
     grad_at<K, T>(m, s_tab, q3, XW, Gw);
     Kin<T> kk;
     if (kinematics(H, kk)) {
-      T wq = w12 * s_tab[K::Dm::TW + q3];
+      T wq = w12 * sW[q3];
       // F - F^-T = (H + H^T + H H^T) F^-T
       T Bm[9];
 #pragma unroll
