@@ -128,11 +128,11 @@ struct Op {
 
 template <typename T>
 int apply_op(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *v, T *y, Reduce red,
-             int do_red, const int *skip, hipStream_t st) {
+             int do_red, const int *skip, hipStream_t st, const PUpd<T> *pu = nullptr) {
   if (op.kind == 2) return launch_mass<T>(c->P, mk<T>(c), op.rho, v, y, 1, red, do_red, skip, st);
+  if (do_red) return -2;
   return launch_tangent<T>(c->P, mk<T>(c), mat->mu, mat->lam, op.kind == 1 ? op.ulin : nullptr,
-                           op.kind == 0 ? op.state : nullptr, op.msr, v, y, 1, red, do_red, skip,
-                           st);
+                           op.kind == 0 ? op.state : nullptr, op.msr, v, y, 1, pu, skip, st);
 }
 
 // Residual replacement ("reliable updates") of the mixed-precision CG: the
@@ -148,7 +148,7 @@ struct Replace {
 };
 
 int do_replace(sdme_ctx *c, const sdme_material *mat, Replace &rep, float *x32, float *r32,
-               const float *d32, float *p32, PcgDev *s, hipStream_t st) {
+               const float *d32, float *p32, PcgDev *s, bool update_p, hipStream_t st) {
   int64_t N = 3 * c->Nn;
   if (launch_add_scaled_f(rep.x64, x32, 1.0, N, st) || launch_fill<float>(x32, 0.0f, N, st) ||
       launch_fill<double>(rep.Ap64, 0.0, N, st))
@@ -156,18 +156,20 @@ int do_replace(sdme_ctx *c, const sdme_material *mat, Replace &rep, float *x32, 
   Reduce none{c->partials, c->counter, c->results + 8};
   if (apply_op<double>(c, mat, *rep.op64, rep.x64, rep.Ap64, none, 0, nullptr, st) ||
       launch_axpbypcz(rep.r64, 1.0, rep.bm, 0.0, -1.0, rep.Ap64, N, st) ||
-      launch_pcg_replace(r32, rep.r64, d32, p32, s, rep.delta, N, red_at(c, 2), st))
+      launch_pcg_replace(r32, rep.r64, d32, p32, s, rep.delta, N, red_at(c, 2), update_p, st))
     return SDME_EDEVICE;
   rep.count++;
   return SDME_OK;
 }
 
 // Jacobi PCG in precision T on vectors of type T: b masked on input, x out.
-// The operator's p^T A p comes from a separate streaming dot product.
+// The operator's p^T A p comes from a separate streaming dot product.  With
+// a second direction buffer p2 and the stored-state operator, the update
+// p = z + beta p is fused into the operator's gather (p and p2 alternate).
 template <typename T>
 int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b, T *x, const T *d,
              double rtol, int maxit, T *r, T *p, T *Ap, int slot, int *iters, double *rel,
-             hipStream_t st, Replace *rep = nullptr) {
+             hipStream_t st, Replace *rep = nullptr, T *p2 = nullptr) {
   int64_t N = 3 * c->Nn;
   PcgDev *s = c->pcg + slot;
   if (launch_fill<T>(x, T(0), N, st) || launch_fill<T>(Ap, T(0), N, st) ||
@@ -176,17 +178,23 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
   if (launch_pcg_init<T>(r, d, p, s, rtol, maxit, rep ? rep->delta : 0.0, N, red_at(c, 2), st))
     return SDME_EDEVICE;
   Reduce none{c->partials, c->counter, c->results + 8};
+  const bool fused = p2 != nullptr && op.kind == 0;
+  T *pb[2] = {p, p2};
+  int par = 0;  // pb[par] holds the current search direction
   for (;;) {
     if (hipMemcpyAsync(c->h_pcg + slot, s, sizeof(PcgDev), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return SDME_EDEVICE;
     int done = c->h_pcg[slot].done;
+    // launched iterations past a stop return at once, so the direction
+    // buffers alternate with the iterations that ran
+    if (fused) par = c->h_pcg[slot].iters & 1;
     if constexpr (sizeof(T) == 4) {
       if (rep && (done == 5 || done == 1)) {
         // the FP32 residual met the replacement or the stop threshold: replace
         // it by the FP64 defect; stop only if that defect meets the tolerance
         if (rep->count >= 1000) return SDME_ENOCONV;
-        int rc = do_replace(c, mat, *rep, x, r, d, p, s, st);
+        int rc = do_replace(c, mat, *rep, x, r, d, pb[par], s, !fused, st);
         if (rc) return rc;
         if (hipMemcpyAsync(c->h_pcg + slot, s, sizeof(PcgDev), hipMemcpyDeviceToHost, st) !=
                 hipSuccess ||
@@ -199,13 +207,22 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
     int it0 = c->h_pcg[slot].iters;
     for (int j = 0; j < CHUNK; j++) {
       if (c->prof && hipEventRecord(c->ev[2 * j], st) != hipSuccess) return SDME_EDEVICE;
-      if (apply_op<T>(c, mat, op, p, Ap, none, 0, &s->done, st)) return SDME_EDEVICE;
+      T *pc = pb[par];
+      if (fused) {
+        // p_new = z + beta p_old formed in the operator's gather
+        PUpd<T> pu{r, d, pb[par ^ 1], &s->beta};
+        if (apply_op<T>(c, mat, op, pc, Ap, none, 0, &s->done, st, &pu)) return SDME_EDEVICE;
+        par ^= 1;
+        pc = pb[par];
+      } else if (apply_op<T>(c, mat, op, pc, Ap, none, 0, &s->done, st)) {
+        return SDME_EDEVICE;
+      }
       if (c->prof && hipEventRecord(c->ev[2 * j + 1], st) != hipSuccess) return SDME_EDEVICE;
       // p^T A p by a separate streaming dot (measured faster than partial sums
       // fused into the operator kernel)
-      if (launch_pcg_pap<T>(p, Ap, s, N, red_at(c, 6), st)) return SDME_EDEVICE;
-      if (launch_pcg_update<T>(x, r, p, Ap, d, s, N, red_at(c, 4), st)) return SDME_EDEVICE;
-      if (launch_pcg_pupdate<T>(p, r, d, s, N, st)) return SDME_EDEVICE;
+      if (launch_pcg_pap<T>(pc, Ap, s, N, red_at(c, 6), st)) return SDME_EDEVICE;
+      if (launch_pcg_update<T>(x, r, pc, Ap, d, s, N, red_at(c, 4), st)) return SDME_EDEVICE;
+      if (!fused && launch_pcg_pupdate<T>(pc, r, d, s, N, st)) return SDME_EDEVICE;
     }
     if (c->prof) {
       // count only the iterations that ran (later ones return at once)
@@ -237,9 +254,10 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
 
 // Workspace plan of a linear solve with given precision.
 struct LinWs {
-  double *d64 = nullptr, *r64 = nullptr, *p64 = nullptr, *Ap64 = nullptr, *bm = nullptr;
-  float *d32 = nullptr, *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *e32 = nullptr,
-        *b32 = nullptr;
+  double *d64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *Ap64 = nullptr,
+         *bm = nullptr;
+  float *d32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *Ap32 = nullptr,
+        *e32 = nullptr, *b32 = nullptr;
   float *state32 = nullptr;
 };
 
@@ -248,12 +266,14 @@ void plan_lin(sdme_ctx *c, int prec, bool need_state32, Bump &b, LinWs &w) {
   w.d64 = b.get<double>(N);
   w.r64 = b.get<double>(N);
   w.p64 = b.get<double>(N);
+  w.q64 = b.get<double>(N);
   w.Ap64 = b.get<double>(N);
   w.bm = b.get<double>(N);
   if (prec == SDME_FP32) {
     w.d32 = b.get<float>(N);
     w.r32 = b.get<float>(N);
     w.p32 = b.get<float>(N);
+    w.q32 = b.get<float>(N);
     w.Ap32 = b.get<float>(N);
     w.e32 = b.get<float>(N);
     w.b32 = b.get<float>(N);
@@ -282,7 +302,7 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
   double rel = 0;
   if (prec == SDME_FP64) {
     int rc = pcg_core<double>(c, mat, op64, w.bm, x, w.d64, rtol, maxit, w.r64, w.p64, w.Ap64, 0,
-                              &its, &rel, st);
+                              &its, &rel, st, nullptr, w.q64);
     if (stats) {
       stats->iterations += its;
       stats->rel_residual = rel;
@@ -300,7 +320,7 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
   Op<float> op32{mass_only ? 2 : 0, w.state32, nullptr, (float)(shift * mat->rho), (float)mat->rho};
   Replace rep{&op64, x, w.r64, w.Ap64, w.bm, inner_rtol, 0};
   int rc = pcg_core<float>(c, mat, op32, w.b32, w.e32, w.d32, rtol, maxit, w.r32, w.p32, w.Ap32, 1,
-                           &its, &rel, st, &rep);
+                           &its, &rel, st, &rep, w.q32);
   // on an early stop the FP32 part accumulated since the last replacement
   // still belongs to the iterate
   if ((rc == SDME_EBREAKDOWN || rc == SDME_ENOCONV) && launch_add_scaled_f(x, w.e32, 1.0, N, st))
@@ -632,12 +652,12 @@ extern "C" int sdme_tangent_apply(sdme_ctx *c, const sdme_material *mat, int pre
     if (launch_fill<double>((double *)y, 0.0, N, st)) return SDME_EDEVICE;
     rc = lerr(launch_tangent<double>(c->P, c->m64, mat->mu, mat->lam, (const double *)u_lin,
                                      (const double *)state, mass_shift * mat->rho,
-                                     (const double *)v, (double *)y, mask, none, 0, nullptr, st));
+                                     (const double *)v, (double *)y, mask, nullptr, nullptr, st));
   } else {
     if (launch_fill<float>((float *)y, 0.0f, N, st)) return SDME_EDEVICE;
     rc = lerr(launch_tangent<float>(c->P, c->m32, mat->mu, mat->lam, (const float *)u_lin,
                                     (const float *)state, (float)(mass_shift * mat->rho),
-                                    (const float *)v, (float *)y, mask, none, 0, nullptr, st));
+                                    (const float *)v, (float *)y, mask, nullptr, nullptr, st));
   }
   if (rc) return rc;
   if ((flags & SDME_CHECK_JAC) && u_lin) return read_flag(c, st);
@@ -1125,7 +1145,7 @@ extern "C" int sdme_lambda_max(sdme_ctx *c, const sdme_material *mat, const doub
     // y = (K_T + K_c) x ; lam = x^T y / x^T M x
     if (launch_fill<double>(y, 0.0, N, st) ||
         launch_tangent<double>(c->P, c->m64, mat->mu, mat->lam, nullptr, state, 0.0, x, y, 1,
-                               none, 0, nullptr, st))
+                               nullptr, nullptr, st))
       return SDME_EDEVICE;
     if (ct && launch_face(c->P, c->m64, 2, 4, nullptr, 1.0, ct->eps, 0, 0, x, y, red_at(c, 11), 0, st))
       return SDME_EDEVICE;
@@ -1180,7 +1200,7 @@ extern "C" int sdme_explicit_adjoint_step(sdme_ctx *c, const sdme_material *mat,
     if ((rc = clear_flag(c, st)) == SDME_OK) {
       if (launch_fill<double>(w.t1, 0.0, N, st) ||
           launch_tangent<double>(c->P, c->m64, mat->mu, mat->lam, u_n, nullptr, 0.0, w.a, w.t1, 1,
-                                 none, 0, nullptr, st) ||
+                                 nullptr, nullptr, st) ||
           launch_axpbypcz(w.t2, 2.0, lam_next, 0.0, -1.0, lam_next2, N, st) ||
           launch_axpbypcz(w.t2, -dt * dt, w.t1, 1.0, 0.0, nullptr, N, st) ||
           launch_bc<double>(w.t2, 0, c->m64, st) ||

@@ -12,7 +12,7 @@ int launch_force_t(const MeshK<T> &, const double *, const double *, const T *, 
                    hipStream_t);
 template <int P, typename T>
 int launch_tangent_t(const MeshK<T> &, const double *, const double *, const T *, const T *, T,
-                     const T *, T *, int, Reduce, int, const int *, hipStream_t);
+                     const T *, T *, int, const PUpd<T> *, const int *, hipStream_t);
 template <int P, typename T>
 int launch_mass_t(const MeshK<T> &, T, const T *, T *, int, Reduce, int, const int *, hipStream_t);
 template <int P, typename T>
@@ -47,9 +47,9 @@ int launch_force(int P, const MeshK<T> &m, const double *mu, const double *lam, 
 }
 template <typename T>
 int launch_tangent(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
-                   const T *state, T msr, const T *v, T *y, int mask, Reduce red, int do_red,
+                   const T *state, T msr, const T *v, T *y, int mask, const PUpd<T> *pu,
                    const int *skip, hipStream_t st) {
-#define C(p) launch_tangent_t<p, T>(m, mu, lam, ulin, state, msr, v, y, mask, red, do_red, skip, st)
+#define C(p) launch_tangent_t<p, T>(m, mu, lam, ulin, state, msr, v, y, mask, pu, skip, st)
   SDME_DISPATCH(P, C)
 #undef C
 }
@@ -99,10 +99,10 @@ template int launch_force<float>(int, const MeshK<float> &, const double *, cons
                                  const float *, float *, float *, int, hipStream_t);
 template int launch_tangent<double>(int, const MeshK<double> &, const double *, const double *,
                                     const double *, const double *, double, const double *,
-                                    double *, int, Reduce, int, const int *, hipStream_t);
+                                    double *, int, const PUpd<double> *, const int *, hipStream_t);
 template int launch_tangent<float>(int, const MeshK<float> &, const double *, const double *,
                                    const float *, const float *, float, const float *, float *,
-                                   int, Reduce, int, const int *, hipStream_t);
+                                   int, const PUpd<float> *, const int *, hipStream_t);
 template int launch_mass<double>(int, const MeshK<double> &, double, const double *, double *,
                                  int, Reduce, int, const int *, hipStream_t);
 template int launch_mass<float>(int, const MeshK<float> &, float, const float *, float *, int,

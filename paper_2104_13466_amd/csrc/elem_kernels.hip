@@ -167,6 +167,36 @@ __device__ __forceinline__ void lds_row(const T *p, T (&r)[N]) {
   for (int k = 0; k < N; k++) r[k] = a[k];
 }
 
+// Gather of the PCG operator's input with the fused search-direction update:
+// tile = p = r dinv + beta pold, and p stored to pu.pnew by the block that
+// owns the slot (the slots on the tile's upper x, y and z faces belong to the
+// neighbouring run or row unless they lie on the mesh boundary; every block
+// computes identical values for shared slots).
+template <class K, typename T>
+__device__ __forceinline__ void gather_tile_pu(const MeshK<T> &m, const Slab &s,
+                                               const int64_t *s_row, const PUpd<T> &pu,
+                                               const T *__restrict__ pold, T beta, bool mask,
+                                               T *tile) {
+  constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
+  const int xe = m.Nx - s.x0;
+  const bool chk = mask && s.bnd;
+  const bool top_y = s.ey == m.ny - 1, top_z = s.ez == m.nz - 1;
+  const T *__restrict__ r = pu.r;
+  const T *__restrict__ d = pu.dinv;
+  T *__restrict__ pn = pu.pnew;
+  tile_for<K>([&](int idx, int rr, int x) {
+    T val = T(0);
+    if (x < xe) {
+      const int64_t g = s_row[rr] + x;
+      val = r[g] * d[g] + beta * pold[g];
+      const int b = rr % n, c = (rr / n) % n;
+      if ((x < TX - 1 || x == xe - 1) && (b < P || top_y) && (c < P || top_z)) pn[g] = val;
+      if (chk && tile_constrained<K>(m, s, rr, x)) val = T(0);
+    }
+    tile[idx] = val;
+  });
+}
+
 // xi1 contraction of one component: st[0][c][q1][b] = sum_a B[q1][a]
 // u[c][b][a], st[1][c][q1][b] with D (rows of NP); su points at the element's
 // first slot in the tile (rows of stride TX).
@@ -547,13 +577,14 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
 // y = (K_T + s M) v with K_T from the stored state (REC = false; the state
 // of the next Gauss-point slabs is in flight while the current one is
 // processed) or from u_lin recomputed at every Gauss point (REC = true).
-template <int P, int Q, typename T, bool REC, bool MASS>
+template <int P, int Q, typename T, bool REC, bool MASS, bool PU>
 __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     MeshK<T> m, const double *__restrict__ mu, const double *__restrict__ lam,
     const T *__restrict__ ulin, const T *__restrict__ state, T mshift_rho, const T *__restrict__ v,
-    T *__restrict__ y, int mask, const int *__restrict__ skip) {
+    T *__restrict__ y, int mask, PUpd<T> pu, const int *__restrict__ skip) {
   using K = EK<P, Q, T>;
   if (skip && *skip) return;
+  const T beta = PU ? (T)*pu.beta : T(0);
   SDME_SETUP
   constexpr int QQQ = Q * Q * Q;
   constexpr bool PIPE = !REC && K::PIPE;
@@ -565,7 +596,12 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     for (int k = 0; k < 10; k++) Gn[k] = sp[k * QQQ];
   }
   const T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
-  SDME_GATHER((REC ? ulin : v), (REC ? false : mask != 0))
+  if (PU) {
+    gather_tile_pu<K>(m, s, s_row, pu, v, beta, mask != 0, tile);
+    __syncthreads();
+  } else {
+    SDME_GATHER((REC ? ulin : v), (REC ? false : mask != 0))
+  }
   T XU[3][3][K::n];
   if (REC) {
     forward_lds<K, T, true>(sB, sD, tile, st, s, XU);
@@ -990,21 +1026,24 @@ int launch_force_t(const MeshK<T> &m, const double *mu, const double *lam, const
 
 template <int P, typename T>
 int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
-                     const T *state, T msr, const T *v, T *y, int mask, Reduce red, int do_red,
+                     const T *state, T msr, const T *v, T *y, int mask, const PUpd<T> *pu,
                      const int *skip, hipStream_t st) {
   constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   const bool mass = msr != T(0);
-  (void)red;
-  if (do_red) return -2;  // p^T A p is taken by a separate streaming dot product
-#define SDME_TAN(REC, MASS)                                                                 \
-  hipLaunchKernelGGL((k_tangent<P, Q, T, REC, MASS>), grid, block, 0, st, m, mu, lam, ulin, \
-                     state, msr, v, y, mask, skip)
+  const PUpd<T> none{nullptr, nullptr, nullptr, nullptr};
+  const PUpd<T> &u = pu ? *pu : none;
+#define SDME_TAN(REC, MASS, PU)                                                                 \
+  hipLaunchKernelGGL((k_tangent<P, Q, T, REC, MASS, PU>), grid, block, 0, st, m, mu, lam, ulin, \
+                     state, msr, v, y, mask, u, skip)
   if (ulin) {
-    if (mass) SDME_TAN(true, true); else SDME_TAN(true, false);
+    if (pu) return -2;  // the fused update is provided for the stored-state operator
+    if (mass) SDME_TAN(true, true, false); else SDME_TAN(true, false, false);
+  } else if (pu) {
+    if (mass) SDME_TAN(false, true, true); else SDME_TAN(false, false, true);
   } else {
-    if (mass) SDME_TAN(false, true); else SDME_TAN(false, false);
+    if (mass) SDME_TAN(false, true, false); else SDME_TAN(false, false, false);
   }
 #undef SDME_TAN
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1063,10 +1102,12 @@ template int launch_force_t<SDME_P, float>(const MeshK<float> &, const double *,
                                            const float *, float *, float *, int, hipStream_t);
 template int launch_tangent_t<SDME_P, double>(const MeshK<double> &, const double *, const double *,
                                               const double *, const double *, double, const double *,
-                                              double *, int, Reduce, int, const int *, hipStream_t);
+                                              double *, int, const PUpd<double> *, const int *,
+                                              hipStream_t);
 template int launch_tangent_t<SDME_P, float>(const MeshK<float> &, const double *, const double *,
                                              const float *, const float *, float, const float *,
-                                             float *, int, Reduce, int, const int *, hipStream_t);
+                                             float *, int, const PUpd<float> *, const int *,
+                                             hipStream_t);
 template int launch_mass_t<SDME_P, double>(const MeshK<double> &, double, const double *, double *,
                                            int, Reduce, int, const int *, hipStream_t);
 template int launch_mass_t<SDME_P, float>(const MeshK<float> &, float, const float *, float *, int,

@@ -11,9 +11,19 @@ namespace sdme {
 template <typename T>
 int launch_force(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *u, T *R,
                  T *state, int mask, hipStream_t st);
+// Search-direction update fused into the PCG operator: while gathering its
+// input the operator forms p = r * dinv + beta * v (v = the previous p) and
+// stores p to pnew (every slot once, by the block that owns it).
+template <typename T>
+struct PUpd {
+  const T *r;
+  const T *dinv;
+  T *pnew;
+  const double *beta;
+};
 template <typename T>
 int launch_tangent(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
-                   const T *state, T msr, const T *v, T *y, int mask, Reduce red, int do_red,
+                   const T *state, T msr, const T *v, T *y, int mask, const PUpd<T> *pu,
                    const int *skip, hipStream_t st);
 template <typename T>
 int launch_mass(int P, const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red,
@@ -90,6 +100,6 @@ int launch_pcg_pap_fin(PcgDev *s, Reduce red2, int nb, hipStream_t st);
 // residual replacement: r32 = float(r64); rz = r32.(r32/d); beta = rz/rz_old;
 // done = (r64.r64 <= tol2); upd2 = delta^2 r64.r64; then p = r32/d + beta p
 int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,
-                       double delta, int64_t n, Reduce red2, hipStream_t st);
+                       double delta, int64_t n, Reduce red2, bool update_p, hipStream_t st);
 
 }  // namespace sdme

@@ -200,6 +200,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_init_fin(PcgDev *s, double rtol, in
     s->iters = 0;
     s->maxit = maxit;
     s->pAp = 0;
+    s->beta = 0;
     s->done = (rr <= s->tol2) ? 1 : (std::isfinite(rr) ? 0 : 3);
   }
 }
@@ -282,11 +283,12 @@ __global__ __launch_bounds__(NTV) void k_pcg_pupdate_force(float *p, const float
     p[i] = r[i] * d[i] + beta * p[i];
 }
 int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, PcgDev *s,
-                       double delta, int64_t n, Reduce red2, hipStream_t st) {
+                       double delta, int64_t n, Reduce red2, bool update_p, hipStream_t st) {
   const int nb = grid_for_u(n);
   hipLaunchKernelGGL(k_pcg_replace, dim3(nb), dim3(NTV), 0, st, r32, r64, d, n, red2);
   hipLaunchKernelGGL(k_pcg_replace_fin, dim3(1), dim3(NTV), 0, st, s, delta, red2, nb);
-  hipLaunchKernelGGL(k_pcg_pupdate_force, dim3(grid_for(n)), dim3(NTV), 0, st, p, r32, d, s, n);
+  if (update_p)
+    hipLaunchKernelGGL(k_pcg_pupdate_force, dim3(grid_for(n)), dim3(NTV), 0, st, p, r32, d, s, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
