@@ -73,7 +73,7 @@ def measured_traffic():
         return None
 
 
-def setup(name, kind=None):
+def setup(name, kind=None, k=0.5, lambda_h=100.0):
     import torch
 
     from paper_2104_13466_amd import inputs
@@ -82,7 +82,7 @@ def setup(name, kind=None):
     if kind is not None:
         w["kind"] = kind
     n, L, P = w["n"], w["L"], w["P"]
-    ctx = Context(n, L, P, basis=w["kind"], dirichlet=w["dirichlet"])
+    ctx = Context(n, L, P, basis=w["kind"], k=k, lambda_h=lambda_h, dirichlet=w["dirichlet"])
     lam0, mu0 = inputs.lame(w["E"], w["nu"])
     dev = torch.device("cuda")
     mu = torch.full((ctx.E,), mu0, dtype=torch.float64, device=dev)
@@ -301,50 +301,100 @@ def case_newmark(a):
     import torch
 
     from paper_2104_13466_amd import inputs
-    from paper_2104_13466_amd.sdme import FP32, FP64, Context
+    from paper_2104_13466_amd.sdme import FP32, FP64
     w = inputs.WORKLOADS["cantilever_p4"]
     runs = []
-    lam0, mu0 = inputs.lame(w["E"], w["nu"])
     for kind in (4, 2, 0):
-        ctx = Context(w["n"], w["L"], w["P"], basis=kind, dirichlet=w["dirichlet"])
-        mat = Context.material(torch.full((ctx.E,), mu0, dtype=torch.float64, device="cuda"),
-                               torch.full((ctx.E,), lam0, dtype=torch.float64, device="cuda"),
-                               w["rho"])
-        N = 3 * ctx.Nn
-        funit = torch.zeros(N, dtype=torch.float64, device="cuda")
-        ctx.face_traction(1, [0.0, 0.0, -1.0], funit)
-        flags = ctx.dirichlet_flags()
-        sols = {}
-        for prec, name in ((FP64, "fp64"), (FP32, "mixed")):
-            u = torch.zeros(N, dtype=torch.float64, device="cuda")
-            v = torch.zeros_like(u)
-            acc = torch.zeros_like(u)
-            f = torch.zeros_like(u)
-            tot = {"newton": 0, "pcg_iterations": 0, "replacements": 0}
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(1, 21):
-                f.copy_(funit * (5.0 * k / 20))
-                st = ctx.newmark_newton_step(mat, prec, u, v, acc, f, 0.1)
-                tot["newton"] += st["newton"]
-                tot["pcg_iterations"] += st["iterations"]
-                tot["replacements"] += st["outer"]
-            torch.cuda.synchronize()
-            tot["seconds"] = round(time.perf_counter() - t0, 3)
-            # tip deflection: z-displacement of the slot at (x = 4, y = 0.5, z = 0.5)
-            Nx, Ny = w["n"][0] * w["P"] + 1, w["n"][1] * w["P"] + 1
-            Nz = w["n"][2] * w["P"] + 1
-            g = ((Nz // 2) * Ny + Ny // 2) * Nx + Nx - 1
-            tot["tip_uz"] = u[2 * ctx.Nn + g].item()
-            sols[name] = u
-            runs.append(dict(basis=KIND_NAMES[kind], precision=name, **tot))
-            log("newmark %s %s: %s" % (KIND_NAMES[kind], name, runs[-1]))
-        runs[-1]["max_rel_diff_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
-                                            sols["fp64"].abs().max()).item()
-        del ctx
+        runs.extend(newmark_runs(w, kind, 0.5, 100.0, (FP64, FP32)))
     return {"case": "newmark", "workload": "cantilever_p4: 16x4x4 hexahedra on 4x1x1, P=4, "
             "clamped x=0, tip traction ramped to 5.0 over 20 steps, dt=0.1",
             "dofs": 3 * inputs.num_nodes(w["n"], w["P"]), "runs": runs}
+
+
+def newmark_runs(w, kind, k, lambda_h, precs):
+    """20 Newmark steps of the cantilever workload with one basis, per precision."""
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.sdme import FP64, Context
+    runs = []
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    ctx = Context(w["n"], w["L"], w["P"], basis=kind, k=k, lambda_h=lambda_h,
+                  dirichlet=w["dirichlet"])
+    mat = Context.material(torch.full((ctx.E,), mu0, dtype=torch.float64, device="cuda"),
+                           torch.full((ctx.E,), lam0, dtype=torch.float64, device="cuda"),
+                           w["rho"])
+    N = 3 * ctx.Nn
+    funit = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.face_traction(1, [0.0, 0.0, -1.0], funit)
+    sols = {}
+    for prec, name in [(q, "fp64" if q == FP64 else "mixed") for q in precs]:
+        u = torch.zeros(N, dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(u)
+        acc = torch.zeros_like(u)
+        f = torch.zeros_like(u)
+        tot = {"newton": 0, "pcg_iterations": 0, "replacements": 0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for step in range(1, 21):
+            f.copy_(funit * (5.0 * step / 20))
+            st = ctx.newmark_newton_step(mat, prec, u, v, acc, f, 0.1)
+            tot["newton"] += st["newton"]
+            tot["pcg_iterations"] += st["iterations"]
+            tot["replacements"] += st["outer"]
+        torch.cuda.synchronize()
+        tot["seconds"] = round(time.perf_counter() - t0, 3)
+        # tip deflection: z-displacement of the slot at (x = 4, y = 0.5, z = 0.5)
+        Nx, Ny = w["n"][0] * w["P"] + 1, w["n"][1] * w["P"] + 1
+        Nz = w["n"][2] * w["P"] + 1
+        g = ((Nz // 2) * Ny + Ny // 2) * Nx + Nx - 1
+        tot["tip_uz"] = u[2 * ctx.Nn + g].item()
+        sols[name] = u
+        runs.append(dict(basis=KIND_NAMES[kind], k=k, lambda_h=lambda_h, precision=name,
+                         **tot))
+        log("newmark %s %s: %s" % (KIND_NAMES[kind], name, runs[-1]))
+    if "mixed" in sols and "fp64" in sols:
+        runs[-1]["max_rel_diff_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
+                                            sols["fp64"].abs().max()).item()
+    del ctx
+    return runs
+
+
+def case_params(a):
+    """Basis parameters the paper varies: the SDME-H lambda tied to the Newmark
+    shift (lambda = b1 = 4 / dt^2 = 400 for dt = 0.1) against the default 100
+    on the cantilever, and the SD exponent k = 0, 0.5, 1 on one mixed Newton
+    iteration of the P = 4 compression."""
+    import gc
+
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.sdme import FP32, FP64, MASK_BC
+    w = inputs.WORKLOADS["cantilever_p4"]
+    newmark = []
+    for lam_h in (100.0, 400.0):
+        newmark.extend(newmark_runs(w, 4, 0.5, lam_h, (FP64,)))
+    static = []
+    for kind, k in ((4, 0.0), (4, 0.5), (4, 1.0), (3, 0.0), (3, 1.0), (2, 0.5)):
+        w2, ctx, mat, u0 = setup("compress_p4", kind=kind, k=k)
+        N = 3 * ctx.Nn
+        R = torch.zeros(N, dtype=torch.float64, device="cuda")
+        du = torch.zeros_like(R)
+
+        def one():
+            ctx.internal_force(mat, FP64, u0, R, flags=MASK_BC)
+            ctx.axpby(-1.0, R, 0.0, R)
+            return ctx.jacobi_pcg(mat, FP32, R, du, u_lin=u0, rtol=a.rtol, maxit=30000, check=False)
+        st, ms = timed(one)
+        static.append({"basis": KIND_NAMES[kind], "k": k, "pcg_iterations": st["iterations"],
+                       "status": st["status"], "ms": round(ms, 1)})
+        log("params %s" % static[-1])
+        del ctx, mat, u0, R, du
+        gc.collect()
+        torch.cuda.empty_cache()
+    return {"case": "params", "newmark_cantilever_p4_fp64": newmark,
+            "compress_p4_mixed_newton_iteration": static}
 
 
 def case_explicit(a):
@@ -474,7 +524,7 @@ def main():
                     help="only the per-operator launches, 12 mixed PCG iterations and a 1 GiB "
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint"],
+    ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
     a = ap.parse_args()
@@ -488,7 +538,7 @@ def main():
 
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
-              "adjoint": case_adjoint}[a.case]
+              "adjoint": case_adjoint, "params": case_params}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)
