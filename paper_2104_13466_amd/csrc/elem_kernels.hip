@@ -50,22 +50,6 @@ struct Slab {
   bool bnd;   // the block's tile touches a face carrying Dirichlet constraints
 };
 
-// Blocks are dispatched to the 8 XCDs of the chip round robin (block b to
-// XCD b mod 8), and each XCD has its own L2.  The logical block (the run of
-// elements the block processes) is chosen so that every XCD works through one
-// contiguous part of the mesh: neighbouring runs and rows, which share tile
-// slots, then meet in the same L2.  A bijection on [0, G) (the last G mod 8
-// blocks keep their index).
-#ifndef SDME_XCD_MAP
-#define SDME_XCD_MAP 1
-#endif
-__device__ __forceinline__ int xcd_block(int b, int G) {
-  constexpr int NX = 8;
-  const int per = G / NX;
-  if (!SDME_XCD_MAP || b >= per * NX) return b;
-  return (b % NX) * per + b / NX;
-}
-
 template <class K, typename T>
 __device__ __forceinline__ Slab make_slab(const MeshK<T> &m) {
   Slab s;
@@ -74,8 +58,7 @@ __device__ __forceinline__ Slab make_slab(const MeshK<T> &m) {
   s.i1 = s.t2 % K::Dm::Q;
   s.i2 = s.t2 / K::Dm::Q;
   const int bpr = (m.nx + K::NE - 1) / K::NE;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int k = lb % bpr, row = lb / bpr;
+  const int k = blockIdx.x % bpr, row = blockIdx.x / bpr;
   s.ey = row % m.ny;
   s.ez = row / m.ny;
   const int ex0 = k * K::NE;
