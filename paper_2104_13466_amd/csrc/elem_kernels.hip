@@ -38,6 +38,10 @@ struct EK {
   // contractions); otherwise one slab is prefetched per step.  Chosen by
   // measurement at ~2e7 DOF per order and precision (FP32, P = 4..6).
   static constexpr bool PIPE = sizeof(T) == 4 && P >= 4 && P <= 6;
+  // every element's Q^2 threads lie in one wave (Q^2 divides the wave size):
+  // the element-private LDS exchanges of the contraction stages then need
+  // only a wave-level synchronisation
+  static constexpr bool WAVE_ELEM = 64 % QQ == 0;
 };
 
 // Thread/element coordinates inside a block.  Block b owns the run of NE
@@ -253,6 +257,20 @@ __device__ __forceinline__ void stage2(const T *sB, const T *sD, const T *st, co
   }
 }
 
+// Synchronisation of the threads of one element between contraction stages
+// (exchanges through the element's private LDS regions): a wave barrier with
+// LDS ordering when the element lies in one wave, else a block barrier.
+template <class K>
+__device__ __forceinline__ void elem_sync() {
+  if constexpr (K::WAVE_ELEM) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Forward contractions of the three gathered components (tile, synchronised)
 // into X[comp][kind][c].  With three LDS buffers the xi1 stages of all
 // components run before one barrier; with two, the xi1 stage of one component
@@ -271,6 +289,21 @@ __device__ __forceinline__ void forward_lds(const T *sB, const T *sD, const T *t
     stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
     stage2<K, T, GRAD>(sB, sD, st + SB1, s, X[1]);
     stage2<K, T, GRAD>(sB, sD, st + 2 * SB1, s, X[2]);
+  } else if constexpr (K::WAVE_ELEM) {
+    // element-local exchanges; one block barrier once the tile has been read
+    constexpr bool single = NB == 1;
+    T *st1 = single ? st : st + SB1;
+    stage1<K, T, GRAD>(sB, sD, su, st, s);
+    elem_sync<K>();
+    stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
+    if (single) elem_sync<K>();
+    stage1<K, T, GRAD>(sB, sD, su + CS, st1, s);
+    elem_sync<K>();
+    stage2<K, T, GRAD>(sB, sD, st1, s, X[1]);
+    if (single) elem_sync<K>();
+    stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st, s);
+    __syncthreads();
+    stage2<K, T, GRAD>(sB, sD, st, s, X[2]);
   } else {
     constexpr bool single = NB == 1;
     T *st1 = single ? st : st + SB1;
@@ -458,16 +491,17 @@ __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
                                               const T *__restrict__ vdot, double &dot) {
   constexpr int HB = (K::Dm::DBUF >= 2) ? K::Dm::SB1 : 0;
   write_g<K, T, GRAD>(A[0], sg, s);
-  __syncthreads();
+  __syncthreads();  // also: the zeroed tile is visible to every element
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T *sti = st + (i & 1) * HB;
     stage2t<K, T, GRAD>(sB, sD, sg, sti, s);
-    __syncthreads();
+    elem_sync<K>();
     if (i < 2) write_g<K, T, GRAD>(A[i + 1], sg, s);
     stage1t_tile<K, T, GRAD>(s, i, sB, sD, sti, tile);
-    __syncthreads();
+    if (i < 2) elem_sync<K>();
   }
+  __syncthreads();  // the tile holds every element's contributions
   tile_writeback<K, T, RED>(m, s, s_row, tile, y, mask, vdot, dot);
 }
 
