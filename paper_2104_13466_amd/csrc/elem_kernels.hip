@@ -137,6 +137,38 @@ __device__ __forceinline__ void tile_for(F &&f) {
   }
 }
 
+// The same visit unrolled over the NIT = ceil(TILE / NT) slots of a thread:
+// f(k, idx, r, x) for k = 0 .. NIT - 1 (idx >= TILE, with r >= ROWS, in the
+// last step of some threads).  Two such visits let a thread issue all its
+// loads before it waits for the first.
+template <class K>
+constexpr int tile_nit() {
+  return (K::TILE + K::NT - 1) / K::NT;
+}
+template <class K, typename F>
+__device__ __forceinline__ void tile_for_all(F &&f) {
+  constexpr int TX = K::TX, NT = K::NT, DX = NT % TX, DR = NT / TX;
+  int x = threadIdx.x % TX, r = threadIdx.x / TX;
+#pragma unroll
+  for (int k = 0; k < tile_nit<K>(); k++) {
+    f(k, (int)threadIdx.x + k * NT, r, x);
+    x += DX;
+    r += DR;
+    if (x >= TX) {
+      x -= TX;
+      r += 1;
+    }
+  }
+}
+
+// Global index of tile slot (r, x), clamped into the mesh and the tile rows:
+// an address that is always safe to load (the value is discarded where the
+// slot lies outside).
+template <class K>
+__device__ __forceinline__ int64_t tile_gidx(const int64_t *s_row, int r, int x, int xe) {
+  return s_row[min(r, K::ROWS - 1)] + min(x, xe - 1);
+}
+
 // Is slot x of tile row r a constrained DOF (only blocks with s.bnd)?
 template <class K, typename T>
 __device__ __forceinline__ bool tile_constrained(const MeshK<T> &m, const Slab &s, int r, int x) {
@@ -148,19 +180,19 @@ __device__ __forceinline__ bool tile_constrained(const MeshK<T> &m, const Slab &
 // Cooperative, coalesced load of the block's tile: tile[comp][c][b][x] =
 // v(comp, x0 + x, ey P + b, ez P + c) for x < TX inside the mesh (zero outside
 // and, with mask, on constrained DOFs).
+// All of a thread's loads are requested (unconditionally, at clamped
+// addresses) before the first is used.
 template <class K, typename T>
 __device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, const int64_t *s_row,
                                             const T *__restrict__ v, bool mask, T *tile) {
   const int xe = m.Nx - s.x0;  // tile slots x < xe lie inside the mesh
-  if (mask && s.bnd) {
-    tile_for<K>([&](int idx, int r, int x) {
-      T val = T(0);
-      if (x < xe && !tile_constrained<K>(m, s, r, x)) val = v[s_row[r] + x];
-      tile[idx] = val;
-    });
-  } else {
-    tile_for<K>([&](int idx, int r, int x) { tile[idx] = x < xe ? v[s_row[r] + x] : T(0); });
-  }
+  const bool chk = mask && s.bnd;
+  T val[tile_nit<K>()];
+  tile_for_all<K>([&](int k, int idx, int r, int x) { val[k] = v[tile_gidx<K>(s_row, r, x, xe)]; });
+  tile_for_all<K>([&](int k, int idx, int r, int x) {
+    if (idx < K::TILE)
+      tile[idx] = (x < xe && !(chk && tile_constrained<K>(m, s, r, x))) ? val[k] : T(0);
+  });
 }
 
 // Contiguous, 16-byte aligned LDS row of N values (wide LDS loads).
@@ -188,13 +220,23 @@ __device__ __forceinline__ void gather_tile_pu(const MeshK<T> &m, const Slab &s,
   const T *__restrict__ r = pu.r;
   const T *__restrict__ d = pu.dinv;
   T *__restrict__ pn = pu.pnew;
-  tile_for<K>([&](int idx, int rr, int x) {
+  // all requests first (clamped addresses), then the updates
+  constexpr int NIT = tile_nit<K>();
+  T vr[NIT], vd[NIT], vp[NIT];
+  tile_for_all<K>([&](int k, int idx, int rr, int x) {
+    const int64_t g = tile_gidx<K>(s_row, rr, x, xe);
+    vr[k] = r[g];
+    vd[k] = d[g];
+    vp[k] = pold[g];
+  });
+  tile_for_all<K>([&](int k, int idx, int rr, int x) {
+    if (idx >= K::TILE) return;
     T val = T(0);
     if (x < xe) {
-      const int64_t g = s_row[rr] + x;
-      val = r[g] * d[g] + beta * pold[g];
+      val = vr[k] * vd[k] + beta * vp[k];
       const int b = rr % n, c = (rr / n) % n;
-      if ((x < TX - 1 || x == xe - 1) && (b < P || top_y) && (c < P || top_z)) pn[g] = val;
+      if ((x < TX - 1 || x == xe - 1) && (b < P || top_y) && (c < P || top_z))
+        pn[s_row[rr] + x] = val;
       if (chk && tile_constrained<K>(m, s, rr, x)) val = T(0);
     }
     tile[idx] = val;
@@ -559,11 +601,15 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
                                                            const T *__restrict__ u, T *__restrict__ R,
                                                            T *__restrict__ state, int mask) {
   using K = EK<P, Q, T>;
-  SDME_PROLOGUE(u, false)
+  SDME_SETUP
+  // material of the element (s.e is a valid index also for idle slabs),
+  // requested with the gather and converted after the forward pass
+  const double mud = mu[s.e], lad = lam[s.e];
+  SDME_GATHER(u, false)
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   if (OUT) zero_tile<K>(tile);
-  T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
+  T mue = s.valid ? (T)mud : T(0), lae = s.valid ? (T)lad : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   if (OUT) zero_acc<K>(A);
@@ -629,7 +675,9 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
 #pragma unroll
     for (int k = 0; k < 10; k++) Gn[k] = sp[k * QQQ];
   }
-  const T mue = s.valid ? (T)mu[s.e] : T(0), lae = s.valid ? (T)lam[s.e] : T(0);
+  // material of the element (s.e is a valid index also for idle slabs),
+  // requested with the gather and converted after the forward pass
+  const double mud = mu[s.e], lad = lam[s.e];
   if (PU) {
     gather_tile_pu<K>(m, s, s_row, pu, v, beta, mask != 0, tile);
     __syncthreads();
@@ -661,6 +709,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   zero_tile<K>(tile);
+  const T mue = s.valid ? (T)mud : T(0), lae = s.valid ? (T)lad : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   zero_acc<K>(A);
@@ -951,10 +1000,12 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_energy(MeshK<double>
   using T = double;
   using K = EK<P, Q, T>;
   __shared__ double s_red[(K::NT + 63) / 64];
-  SDME_PROLOGUE(u, false)
+  SDME_SETUP
+  const double mud = mu[s.e], lad = lam[s.e];  // requested with the gather
+  SDME_GATHER(u, false)
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
-  T mue = s.valid ? mu[s.e] : 0.0, lae = s.valid ? lam[s.e] : 0.0;
+  T mue = s.valid ? mud : 0.0, lae = s.valid ? lad : 0.0;
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   double acc = 0;
 #pragma unroll 1
