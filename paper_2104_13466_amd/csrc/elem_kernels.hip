@@ -36,8 +36,8 @@ struct EK {
   // Stored-state tangent action: PIPE selects two named buffers of
   // Gauss-point slabs requested ahead (the first two before the forward
   // contractions); otherwise one slab is prefetched per step.  Chosen by
-  // measurement at ~2e7 DOF per order and precision (FP32, P = 4..6).
-  static constexpr bool PIPE = sizeof(T) == 4 && P >= 4 && P <= 6;
+  // measurement at ~2e7 DOF per order and precision (FP32, P >= 4).
+  static constexpr bool PIPE = sizeof(T) == 4 && P >= 4;
   // every element's Q^2 threads lie in one wave (Q^2 divides the wave size):
   // the element-private LDS exchanges of the contraction stages then need
   // only a wave-level synchronisation

@@ -55,12 +55,11 @@ struct Dims {
     return ne;
   }
   // three buffers (the xi1 stages of all components before one barrier) when
-  // they fit in 80 KiB, else two, else one; at P = 4 two buffers were
-  // measured faster (three: faster at P = 2, 6, 8)
+  // they fit in 80 KiB, else two, else one
 #ifndef SDME_TRIPLE
 #define SDME_TRIPLE 1
 #endif
-  static constexpr int DBUF = (SDME_TRIPLE && P != 4 && lds_words(NE_T, 3) * WORD <= 81920) ? 3
+  static constexpr int DBUF = (SDME_TRIPLE && lds_words(NE_T, 3) * WORD <= 81920) ? 3
                               : (lds_words(1, 2) * WORD <= LDS_CAP)             ? 2
                                                                                 : 1;
   static constexpr int NE = ne_fit(DBUF);
