@@ -89,35 +89,63 @@ __device__ __forceinline__ void load_tables(const MeshK<T> &m, T *s_tab) {
   for (int i = threadIdx.x; i < K::TS; i += K::NT) s_tab[i] = m.tab[i];
 }
 
-// The stage tables of EK (LB .. TSX) from the mesh tables (B, D as [Q][n]).
+// The stage tables of EK (LB .. TSX) from the mesh tables (B, D as [Q][n]):
+// entry i of the LDS tables, requested from global memory with one
+// unconditional load (a valid index; padding entries are zeroed after).
 template <class K, typename T>
-__device__ __forceinline__ void load_stage_tables(const MeshK<T> &m, T *s_tab) {
+__device__ __forceinline__ T stage_table_entry(const MeshK<T> &m, int i) {
   constexpr int n = K::n, Q = K::Dm::Q, NP = K::NP, QP = K::QP;
   using Dm = typename K::Dm;
-  for (int i = threadIdx.x; i < K::TSX; i += K::NT) {
-    T v = T(0);
-    if (i < K::LBT) {  // B, D rows
-      int t = i / (Q * NP), r = i % (Q * NP), q = r / NP, c = r % NP;
-      if (c < n) v = m.tab[(t ? Dm::TD : Dm::TB) + q * n + c];
-    } else if (i < K::LW) {  // Bt, Dt rows
-      int j = i - K::LBT, t = j / (n * QP), r = j % (n * QP), a = r / QP, q = r % QP;
-      if (q < Q) v = m.tab[(t ? Dm::TD : Dm::TB) + q * n + a];
-    } else {
-      v = m.tab[Dm::TW + (i - K::LW)];
-    }
-    s_tab[i] = v;
+  int src = Dm::TB;
+  bool pad = true;
+  if (i < K::LBT) {  // B, D rows
+    const int t = i / (Q * NP), r = i % (Q * NP), q = r / NP, c = r % NP;
+    src = (t ? Dm::TD : Dm::TB) + q * n + c;
+    pad = c >= n;
+  } else if (i < K::LW) {  // Bt, Dt rows
+    const int j = i - K::LBT, t = j / (n * QP), r = j % (n * QP), a = r / QP, q = r % QP;
+    src = (t ? Dm::TD : Dm::TB) + q * n + a;
+    pad = q >= Q;
+  } else if (i < K::TSX) {
+    src = Dm::TW + (i - K::LW);
+    pad = false;
+  }
+  const T v = m.tab[pad ? Dm::TB : src];
+  return pad ? T(0) : v;
+}
+template <class K>
+constexpr int stage_table_nit() {
+  return (K::TSX + K::NT - 1) / K::NT;
+}
+// Request a thread's table entries (registers), then store them to LDS.
+template <class K, typename T>
+__device__ __forceinline__ void request_stage_tables(const MeshK<T> &m,
+                                                     T (&tv)[stage_table_nit<K>()]) {
+#pragma unroll
+  for (int k = 0; k < stage_table_nit<K>(); k++)
+    tv[k] = stage_table_entry<K>(m, (int)threadIdx.x + k * K::NT);
+}
+template <class K, typename T>
+__device__ __forceinline__ void store_stage_tables(const T (&tv)[stage_table_nit<K>()], T *s_tab) {
+#pragma unroll
+  for (int k = 0; k < stage_table_nit<K>(); k++) {
+    const int i = (int)threadIdx.x + k * K::NT;
+    if (i < K::TSX) s_tab[i] = tv[k];
   }
 }
 
-// Global offsets of the rows of the block's tile: row r = (comp n + c) n + b
+// Global offset of row r of the block's tile: row r = (comp n + c) n + b
 // holds the slots (x0 .. x0 + TX - 1, ey P + b, ez P + c) of component comp.
 template <class K, typename T>
-__device__ __forceinline__ void tile_rows(const MeshK<T> &m, const Slab &s, int64_t *s_row) {
+__device__ __forceinline__ int64_t tile_row_offset(const MeshK<T> &m, const Slab &s, int r) {
   constexpr int n = K::n, P = K::Dm::P;
-  for (int r = threadIdx.x; r < K::ROWS; r += K::NT) {
-    int b = r % n, c = (r / n) % n, comp = r / (n * n);
-    s_row[r] = (int64_t)comp * m.Nn + ((int64_t)(s.ez * P + c) * m.Ny + (s.ey * P + b)) * m.Nx + s.x0;
-  }
+  const int b = r % n, c = (r / n) % n, comp = r / (n * n);
+  return (int64_t)comp * m.Nn + ((int64_t)(s.ez * P + c) * m.Ny + (s.ey * P + b)) * m.Nx + s.x0;
+}
+// The row offsets of the tile, in LDS.
+template <class K, typename T>
+__device__ __forceinline__ void tile_rows(const MeshK<T> &m, const Slab &s, int64_t *s_row) {
+  for (int r = threadIdx.x; r < K::ROWS; r += K::NT) s_row[r] = tile_row_offset<K>(m, s, r);
 }
 
 // Visit the tile slots idx = r TX + x, idx = threadIdx.x + k NT, with the
@@ -163,10 +191,12 @@ __device__ __forceinline__ void tile_for_all(F &&f) {
 
 // Global index of tile slot (r, x), clamped into the mesh and the tile rows:
 // an address that is always safe to load (the value is discarded where the
-// slot lies outside).
-template <class K>
-__device__ __forceinline__ int64_t tile_gidx(const int64_t *s_row, int r, int x, int xe) {
-  return s_row[min(r, K::ROWS - 1)] + min(x, xe - 1);
+// slot lies outside).  Computed from the mesh, so that requests can be issued
+// before the row offsets are in LDS.
+template <class K, typename T>
+__device__ __forceinline__ int64_t tile_gidx(const MeshK<T> &m, const Slab &s, int r, int x,
+                                             int xe) {
+  return tile_row_offset<K>(m, s, min(r, K::ROWS - 1)) + min(x, xe - 1);
 }
 
 // Is slot x of tile row r a constrained DOF (only blocks with s.bnd)?
@@ -180,19 +210,34 @@ __device__ __forceinline__ bool tile_constrained(const MeshK<T> &m, const Slab &
 // Cooperative, coalesced load of the block's tile: tile[comp][c][b][x] =
 // v(comp, x0 + x, ey P + b, ez P + c) for x < TX inside the mesh (zero outside
 // and, with mask, on constrained DOFs).
-// All of a thread's loads are requested (unconditionally, at clamped
-// addresses) before the first is used.
+// In two phases: all of a thread's loads are requested (unconditionally, at
+// clamped addresses) into registers, then stored to the tile.
 template <class K, typename T>
-__device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, const int64_t *s_row,
-                                            const T *__restrict__ v, bool mask, T *tile) {
+__device__ __forceinline__ void tile_request(const MeshK<T> &m, const Slab &s,
+                                             const T *__restrict__ v, T (&val)[tile_nit<K>()]) {
   const int xe = m.Nx - s.x0;  // tile slots x < xe lie inside the mesh
+  tile_for_all<K>([&](int k, int idx, int r, int x) { val[k] = v[tile_gidx<K>(m, s, r, x, xe)]; });
+}
+template <class K, typename T>
+__device__ __forceinline__ void tile_store(const MeshK<T> &m, const Slab &s,
+                                           const T (&val)[tile_nit<K>()], bool mask, T *tile) {
+  const int xe = m.Nx - s.x0;
   const bool chk = mask && s.bnd;
-  T val[tile_nit<K>()];
-  tile_for_all<K>([&](int k, int idx, int r, int x) { val[k] = v[tile_gidx<K>(s_row, r, x, xe)]; });
   tile_for_all<K>([&](int k, int idx, int r, int x) {
     if (idx < K::TILE)
       tile[idx] = (x < xe && !(chk && tile_constrained<K>(m, s, r, x))) ? val[k] : T(0);
   });
+}
+// Both phases once the row offsets are in LDS (addresses from s_row).
+template <class K, typename T>
+__device__ __forceinline__ void gather_tile(const MeshK<T> &m, const Slab &s, const int64_t *s_row,
+                                            const T *__restrict__ v, bool mask, T *tile) {
+  const int xe = m.Nx - s.x0;
+  T val[tile_nit<K>()];
+  tile_for_all<K>([&](int k, int idx, int r, int x) {
+    val[k] = v[s_row[min(r, K::ROWS - 1)] + min(x, xe - 1)];
+  });
+  tile_store<K>(m, s, val, mask, tile);
 }
 
 // Contiguous, 16-byte aligned LDS row of N values (wide LDS loads).
@@ -208,32 +253,40 @@ __device__ __forceinline__ void lds_row(const T *p, T (&r)[N]) {
 // owns the slot (the slots on the tile's upper x, y and z faces belong to the
 // neighbouring run or row unless they lie on the mesh boundary; every block
 // computes identical values for shared slots).
+// Requests (registers; clamped addresses) and updates in separate phases,
+// like tile_request and tile_store.
 template <class K, typename T>
-__device__ __forceinline__ void gather_tile_pu(const MeshK<T> &m, const Slab &s,
-                                               const int64_t *s_row, const PUpd<T> &pu,
-                                               const T *__restrict__ pold, T beta, bool mask,
-                                               T *tile) {
+struct PuReq {
+  T r[tile_nit<K>()], d[tile_nit<K>()], p[tile_nit<K>()];
+};
+template <class K, typename T>
+__device__ __forceinline__ void tile_request_pu(const MeshK<T> &m, const Slab &s,
+                                                const PUpd<T> &pu, const T *__restrict__ pold,
+                                                PuReq<K, T> &q) {
+  const int xe = m.Nx - s.x0;
+  const T *__restrict__ r = pu.r;
+  const T *__restrict__ d = pu.dinv;
+  tile_for_all<K>([&](int k, int idx, int rr, int x) {
+    const int64_t g = tile_gidx<K>(m, s, rr, x, xe);
+    q.r[k] = r[g];
+    q.d[k] = d[g];
+    q.p[k] = pold[g];
+  });
+}
+template <class K, typename T>
+__device__ __forceinline__ void tile_store_pu(const MeshK<T> &m, const Slab &s,
+                                              const int64_t *s_row, const PUpd<T> &pu,
+                                              const PuReq<K, T> &q, T beta, bool mask, T *tile) {
   constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
   const int xe = m.Nx - s.x0;
   const bool chk = mask && s.bnd;
   const bool top_y = s.ey == m.ny - 1, top_z = s.ez == m.nz - 1;
-  const T *__restrict__ r = pu.r;
-  const T *__restrict__ d = pu.dinv;
   T *__restrict__ pn = pu.pnew;
-  // all requests first (clamped addresses), then the updates
-  constexpr int NIT = tile_nit<K>();
-  T vr[NIT], vd[NIT], vp[NIT];
-  tile_for_all<K>([&](int k, int idx, int rr, int x) {
-    const int64_t g = tile_gidx<K>(s_row, rr, x, xe);
-    vr[k] = r[g];
-    vd[k] = d[g];
-    vp[k] = pold[g];
-  });
   tile_for_all<K>([&](int k, int idx, int rr, int x) {
     if (idx >= K::TILE) return;
     T val = T(0);
     if (x < xe) {
-      val = vr[k] * vd[k] + beta * vp[k];
+      val = q.r[k] * q.d[k] + beta * q.p[k];
       const int b = rr % n, c = (rr / n) % n;
       if ((x < TX - 1 || x == xe - 1) && (b < P || top_y) && (c < P || top_z))
         pn[s_row[rr] + x] = val;
@@ -574,24 +627,34 @@ __device__ __forceinline__ void block_partial_t(double v, Reduce red, double *s_
   }
 }
 
-// Common kernel prologue: tables, slab coordinates and tile row offsets
-// (SDME_SETUP, ends with a barrier), then the first field gathered into the
-// tile (SDME_GATHER, ends with a barrier).
-#define SDME_SETUP                                                              \
+// Common kernel prologue.  SDME_SETUP_A: slab coordinates and LDS pointers;
+// the thread's basis-table entries are requested.  The kernel then requests
+// its other inputs (SDME_REQUEST: the first field of the tile), so that all
+// are in flight together.  SDME_SETUP_B: tile row offsets and tables stored
+// to LDS (waits only for the table requests, the first issued), barrier.
+// SDME_STORE: the requested field stored to the tile, barrier.
+#define SDME_SETUP_A                                                            \
   __shared__ __align__(16) T smem[K::SMEM];                                     \
   int64_t *s_row = (int64_t *)smem;                                             \
   T *tile = smem + K::RW + K::NE * K::SE, *s_tab = tile + K::TILEP;             \
-  load_stage_tables<K>(m, s_tab);                                               \
   Slab s = make_slab<K>(m);                                                     \
-  tile_rows<K>(m, s, s_row);                                                    \
+  T s_tv[stage_table_nit<K>()];                                                 \
+  request_stage_tables<K>(m, s_tv);                                             \
   T *su = smem + K::RW + s.le * K::SE, *st = su + K::SA;                        \
   const T *sB = s_tab + K::LB, *sD = s_tab + K::LD, *sW = s_tab + K::LW;       \
-  const T *sBt = s_tab + K::LBT, *sDt = s_tab + K::LDT;                         \
+  const T *sBt = s_tab + K::LBT, *sDt = s_tab + K::LDT;
+#define SDME_SETUP_B                                                            \
+  tile_rows<K>(m, s, s_row);                                                    \
+  store_stage_tables<K>(s_tv, s_tab);                                           \
   __syncthreads();
-#define SDME_GATHER(FIELD, MASK)                                                \
-  gather_tile<K>(m, s, s_row, FIELD, MASK, tile);                               \
+#define SDME_REQUEST(FIELD)                                                     \
+  T s_gv[tile_nit<K>()];                                                        \
+  tile_request<K>(m, s, FIELD, s_gv);
+#define SDME_STORE(MASK)                                                        \
+  tile_store<K>(m, s, s_gv, MASK, tile);                                        \
   __syncthreads();
-#define SDME_PROLOGUE(FIELD, MASK) SDME_SETUP SDME_GATHER(FIELD, MASK)
+#define SDME_PROLOGUE(FIELD, MASK) \
+  SDME_SETUP_A SDME_REQUEST(FIELD) SDME_SETUP_B SDME_STORE(MASK)
 
 // ===================================================================== force
 // R(u) (and optionally the linearisation state of u).
@@ -601,11 +664,13 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
                                                            const T *__restrict__ u, T *__restrict__ R,
                                                            T *__restrict__ state, int mask) {
   using K = EK<P, Q, T>;
-  SDME_SETUP
+  SDME_SETUP_A
   // material of the element (s.e is a valid index also for idle slabs),
   // requested with the gather and converted after the forward pass
   const double mud = mu[s.e], lad = lam[s.e];
-  SDME_GATHER(u, false)
+  SDME_SETUP_B
+  gather_tile<K>(m, s, s_row, u, false, tile);
+  __syncthreads();
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   if (OUT) zero_tile<K>(tile);
@@ -665,7 +730,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   using K = EK<P, Q, T>;
   if (skip && *skip) return;
   const T beta = PU ? (T)*pu.beta : T(0);
-  SDME_SETUP
+  SDME_SETUP_A
   constexpr int QQQ = Q * Q * Q;
   constexpr bool PIPE = !REC && K::PIPE;
   const T *__restrict__ sp = state + (size_t)(s.valid ? s.e : 0) * 10 * QQQ + s.t2;
@@ -678,11 +743,16 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   // material of the element (s.e is a valid index also for idle slabs),
   // requested with the gather and converted after the forward pass
   const double mud = mu[s.e], lad = lam[s.e];
-  if (PU) {
-    gather_tile_pu<K>(m, s, s_row, pu, v, beta, mask != 0, tile);
+  if constexpr (PU) {
+    PuReq<K, T> q;
+    tile_request_pu<K>(m, s, pu, v, q);
+    SDME_SETUP_B
+    tile_store_pu<K>(m, s, s_row, pu, q, beta, mask != 0, tile);
     __syncthreads();
   } else {
-    SDME_GATHER((REC ? ulin : v), (REC ? false : mask != 0))
+    SDME_REQUEST((REC ? ulin : v))
+    SDME_SETUP_B
+    SDME_STORE((REC ? false : mask != 0))
   }
   T XU[3][3][K::n];
   if (REC) {
@@ -1000,9 +1070,11 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_energy(MeshK<double>
   using T = double;
   using K = EK<P, Q, T>;
   __shared__ double s_red[(K::NT + 63) / 64];
-  SDME_SETUP
+  SDME_SETUP_A
   const double mud = mu[s.e], lad = lam[s.e];  // requested with the gather
-  SDME_GATHER(u, false)
+  SDME_SETUP_B
+  gather_tile<K>(m, s, s_row, u, false, tile);
+  __syncthreads();
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
   T mue = s.valid ? mud : 0.0, lae = s.valid ? lad : 0.0;
