@@ -26,10 +26,13 @@ struct EK {
   static constexpr int TX = Dm::TX, TILE = Dm::TILE, ROWS = Dm::ROWS, RW = Dm::RW;
   static constexpr int NP = Dm::NP, QP = Dm::QP, TILEP = Dm::rup(TILE);
   // basis tables as the contraction stages read them from LDS (rows padded
-  // and aligned for wide loads): B, D as [Q][NP]; their transposes Bt, Dt as
-  // [n][QP]; the weights W[Q]
-  static constexpr int LB = 0, LD = Dm::Q * NP, LBT = 2 * Dm::Q * NP, LDT = LBT + n * QP,
-                       LW = LDT + n * QP, TSX = LW + Dm::Q;
+  // and aligned for wide loads): B as [Q][NP]; D scaled by 2/h of direction
+  // d = 0, 1, 2 as [Q][NP] at LD + d DS (contractions with them give physical
+  // derivatives); the transpose Bt and the scaled Dt of directions 0, 1 as
+  // [n][QP] (at LDT + d DTS); the weights W[Q]
+  static constexpr int DS = Dm::Q * NP, DTS = n * QP;
+  static constexpr int LB = 0, LD = DS, LBT = 4 * DS, LDT = LBT + DTS, LW = LDT + 2 * DTS,
+                       TSX = LW + Dm::Q;
   // shared memory words of a block: row offsets, per-element regions, the
   // tile, tables
   static constexpr int SMEM = RW + NE * SE + TILEP + TSX;
@@ -96,14 +99,16 @@ template <class K, typename T>
 __device__ __forceinline__ T stage_table_entry(const MeshK<T> &m, int i) {
   constexpr int n = K::n, Q = K::Dm::Q, NP = K::NP, QP = K::QP;
   using Dm = typename K::Dm;
-  int src = Dm::TB;
+  int src = Dm::TB, t = 0;
   bool pad = true;
-  if (i < K::LBT) {  // B, D rows
-    const int t = i / (Q * NP), r = i % (Q * NP), q = r / NP, c = r % NP;
+  if (i < K::LBT) {  // B, D rows (t = 0: B; 1..3: D scaled by 2/h of direction t - 1)
+    const int r = i % K::DS, q = r / NP, c = r % NP;
+    t = i / K::DS;
     src = (t ? Dm::TD : Dm::TB) + q * n + c;
     pad = c >= n;
-  } else if (i < K::LW) {  // Bt, Dt rows
-    const int j = i - K::LBT, t = j / (n * QP), r = j % (n * QP), a = r / QP, q = r % QP;
+  } else if (i < K::LW) {  // Bt, Dt rows (t = 0: Bt; 1, 2: Dt of direction t - 1)
+    const int j = i - K::LBT, r = j % K::DTS, a = r / QP, q = r % QP;
+    t = j / K::DTS;
     src = (t ? Dm::TD : Dm::TB) + q * n + a;
     pad = q >= Q;
   } else if (i < K::TSX) {
@@ -111,7 +116,8 @@ __device__ __forceinline__ T stage_table_entry(const MeshK<T> &m, int i) {
     pad = false;
   }
   const T v = m.tab[pad ? Dm::TB : src];
-  return pad ? T(0) : v;
+  const T sc = t == 1 ? m.ih[0] : t == 2 ? m.ih[1] : t == 3 ? m.ih[2] : T(1);
+  return pad ? T(0) : v * sc;
 }
 template <class K>
 constexpr int stage_table_nit() {
@@ -367,7 +373,7 @@ __device__ __forceinline__ void elem_sync() {
 }
 
 // Forward contractions of the three gathered components (tile, synchronised)
-// into X[comp][kind][c].  With three LDS buffers the xi1 stages of all
+// into X[comp][kind][c]; sD: the scaled D tables, direction 0 first.  With three LDS buffers the xi1 stages of all
 // components run before one barrier; with two, the xi1 stage of one component
 // overlaps the xi2 stage of the previous one; with one, extra barriers.  Ends
 // after a barrier that follows the last read of the tile.
@@ -376,43 +382,44 @@ __device__ __forceinline__ void forward_lds(const T *sB, const T *sD, const T *t
                                             const Slab &s, T (&X)[3][3][K::n]) {
   constexpr int n = K::n, SB1 = K::Dm::SB1, CS = n * n * K::TX, NB = K::Dm::DBUF;
   const T *su = tile + s.le * K::Dm::P;
+  const T *sD2 = sD + K::DS;
   if constexpr (NB == 3) {
     stage1<K, T, GRAD>(sB, sD, su, st, s);
     stage1<K, T, GRAD>(sB, sD, su + CS, st + SB1, s);
     stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st + 2 * SB1, s);
     __syncthreads();
-    stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
-    stage2<K, T, GRAD>(sB, sD, st + SB1, s, X[1]);
-    stage2<K, T, GRAD>(sB, sD, st + 2 * SB1, s, X[2]);
+    stage2<K, T, GRAD>(sB, sD2, st, s, X[0]);
+    stage2<K, T, GRAD>(sB, sD2, st + SB1, s, X[1]);
+    stage2<K, T, GRAD>(sB, sD2, st + 2 * SB1, s, X[2]);
   } else if constexpr (K::WAVE_ELEM) {
     // element-local exchanges; one block barrier once the tile has been read
     constexpr bool single = NB == 1;
     T *st1 = single ? st : st + SB1;
     stage1<K, T, GRAD>(sB, sD, su, st, s);
     elem_sync<K>();
-    stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
+    stage2<K, T, GRAD>(sB, sD2, st, s, X[0]);
     if (single) elem_sync<K>();
     stage1<K, T, GRAD>(sB, sD, su + CS, st1, s);
     elem_sync<K>();
-    stage2<K, T, GRAD>(sB, sD, st1, s, X[1]);
+    stage2<K, T, GRAD>(sB, sD2, st1, s, X[1]);
     if (single) elem_sync<K>();
     stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st, s);
     __syncthreads();
-    stage2<K, T, GRAD>(sB, sD, st, s, X[2]);
+    stage2<K, T, GRAD>(sB, sD2, st, s, X[2]);
   } else {
     constexpr bool single = NB == 1;
     T *st1 = single ? st : st + SB1;
     stage1<K, T, GRAD>(sB, sD, su, st, s);
     __syncthreads();
-    stage2<K, T, GRAD>(sB, sD, st, s, X[0]);
+    stage2<K, T, GRAD>(sB, sD2, st, s, X[0]);
     if (single) __syncthreads();
     stage1<K, T, GRAD>(sB, sD, su + CS, st1, s);
     __syncthreads();
-    stage2<K, T, GRAD>(sB, sD, st1, s, X[1]);
+    stage2<K, T, GRAD>(sB, sD2, st1, s, X[1]);
     if (single) __syncthreads();
     stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st, s);
     __syncthreads();
-    stage2<K, T, GRAD>(sB, sD, st, s, X[2]);
+    stage2<K, T, GRAD>(sB, sD2, st, s, X[2]);
   }
 }
 
@@ -424,7 +431,7 @@ __device__ __forceinline__ void grad_at(const MeshK<T> &m, const T *tab, int q3,
   constexpr int n = K::n;
   T bq[n], dq[n];
   lds_row<n>(tab + K::LB + q3 * K::NP, bq);
-  lds_row<n>(tab + K::LD + q3 * K::NP, dq);
+  lds_row<n>(tab + K::LD + 2 * K::DS + q3 * K::NP, dq);
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T g0 = T(0), g1 = T(0), g2 = T(0);
@@ -434,9 +441,9 @@ __device__ __forceinline__ void grad_at(const MeshK<T> &m, const T *tab, int q3,
       g1 += bq[c] * X[i][1][c];
       g2 += dq[c] * X[i][0][c];
     }
-    H[i * 3 + 0] = g0 * m.ih[0];
-    H[i * 3 + 1] = g1 * m.ih[1];
-    H[i * 3 + 2] = g2 * m.ih[2];
+    H[i * 3 + 0] = g0;
+    H[i * 3 + 1] = g1;
+    H[i * 3 + 2] = g2;
   }
 }
 
@@ -455,14 +462,15 @@ __device__ __forceinline__ void value_at(const T *tab, int q3, const T (&X)[3][3
 }
 
 // Transposed xi3 contraction: accumulate flux f (already scaled by the
-// quadrature weight, detJ and 2/h) and a value-type flux mv into A.
+// quadrature weight and detJ; the 2/h factors are in the D tables) and a
+// value-type flux mv into A.
 template <class K, typename T, bool GRAD, bool VAL>
 __device__ __forceinline__ void accum_at(const T *tab, int q3, const T f[9], const T mv[3],
                                          T (&A)[3][3][K::n]) {
   constexpr int n = K::n;
   T bq[n], dq[n];
   lds_row<n>(tab + K::LB + q3 * K::NP, bq);
-  if (GRAD) lds_row<n>(tab + K::LD + q3 * K::NP, dq);
+  if (GRAD) lds_row<n>(tab + K::LD + 2 * K::DS + q3 * K::NP, dq);
 #pragma unroll
   for (int c = 0; c < n; c++) {
 #pragma unroll
@@ -577,7 +585,8 @@ __device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s,
 // Transposes of the xi2 and xi1 contractions for the three components,
 // accumulated into the block's tile (zeroed by the caller after the forward
 // pass), then written back to y.  The flux write of component i+1 overlaps
-// the xi1 stage of component i (sg and the st buffers alternate).
+// the xi1 stage of component i (sg and the st buffers alternate).  sD: the
+// scaled transposed D tables, direction 0 then 1.
 template <class K, typename T, bool GRAD, bool RED>
 __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
                                               const T (&A)[3][3][K::n], const T *sB, const T *sD,
@@ -590,7 +599,7 @@ __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T *sti = st + (i & 1) * HB;
-    stage2t<K, T, GRAD>(sB, sD, sg, sti, s);
+    stage2t<K, T, GRAD>(sB, sD + K::DTS, sg, sti, s);
     elem_sync<K>();
     if (i < 2) write_g<K, T, GRAD>(A[i + 1], sg, s);
     stage1t_tile<K, T, GRAD>(s, i, sB, sD, sti, tile);
@@ -699,14 +708,10 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
       sp[9 * QQQ + q3 * K::QQ] = mue - lae * kk.lnJ;
     }
     if (OUT) {
-      T Pk[9], f[9], mv[3] = {T(0), T(0), T(0)};
-      first_pk(H, kk, mue, lae, Pk);
-      T wq = w12 * sW[q3];
-      if (!ok) wq = T(0);
-#pragma unroll
-      for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int J = 0; J < 3; J++) f[i * 3 + J] = Pk[i * 3 + J] * wq * m.ih[J];
+      // P is linear in (mu, lam): the quadrature weight enters through them
+      T f[9], mv[3] = {T(0), T(0), T(0)};
+      const T wq = ok ? w12 * sW[q3] : T(0);
+      first_pk(H, kk, wq * mue, wq * lae, f);
       accum_at<K, T, true, false>(s_tab, q3, f, mv, A);
     }
   }
@@ -783,7 +788,9 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
   zero_acc<K>(A);
-  // linearised stress at Gauss point (i1, i2, q3) from G = F^-1, c1:
+  // linearised stress at Gauss point (i1, i2, q3) from G = F^-1, c1 (the
+  // quadrature weight enters through the coefficients, dP being linear in
+  // mu, c1 and lam):
   // dP = mu dF + c1 (G dF G)^T + lam tr(G dF) G^T, one row at a time,
   // accumulated at once into the transposed xi3 contraction (few live
   // temporaries)
@@ -799,12 +806,12 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
       for (int L = 0; L < 3; L++)
         Am[I * 3 + L] = G[I * 3 + 0] * dF[0 * 3 + L] + G[I * 3 + 1] * dF[1 * 3 + L] +
                         G[I * 3 + 2] * dF[2 * 3 + L];
-    const T trl = lae * (Am[0] + Am[4] + Am[8]);
     const T wq = w12 * sW[q3];
-    const T s0 = wq * m.ih[0], s1 = wq * m.ih[1], s2 = wq * m.ih[2];
+    const T wmu = wq * mue, wc1 = wq * c1;
+    const T trl = (wq * lae) * (Am[0] + Am[4] + Am[8]);
     T bq[K::n], dq[K::n];
     lds_row<K::n>(sB + q3 * K::NP, bq);
-    lds_row<K::n>(sD + q3 * K::NP, dq);
+    lds_row<K::n>(sD + 2 * K::DS + q3 * K::NP, dq);
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       T fr[3];
@@ -812,11 +819,8 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
       for (int J = 0; J < 3; J++) {
         T AG = Am[J * 3 + 0] * G[0 * 3 + i] + Am[J * 3 + 1] * G[1 * 3 + i] +
                Am[J * 3 + 2] * G[2 * 3 + i];
-        fr[J] = mue * dF[i * 3 + J] + c1 * AG + trl * G[J * 3 + i];
+        fr[J] = wmu * dF[i * 3 + J] + wc1 * AG + trl * G[J * 3 + i];
       }
-      fr[0] *= s0;
-      fr[1] *= s1;
-      fr[2] *= s2;
       const T mv = MASS ? mshift_rho * wq * val[i] : T(0);
 #pragma unroll
       for (int c = 0; c < K::n; c++) {
