@@ -255,10 +255,12 @@ __device__ __forceinline__ void lds_row(const T *p, T (&r)[N]) {
 }
 
 // Gather of the PCG operator's input with the fused search-direction update:
-// tile = p = r dinv + beta pold, and p stored to pu.pnew by the block that
-// owns the slot (the slots on the tile's upper x, y and z faces belong to the
-// neighbouring run or row unless they lie on the mesh boundary; every block
-// computes identical values for shared slots).
+// tile = p = r dinv + beta pold, and p stored to pu.pnew by every block whose
+// tile holds the slot.  Blocks that share a slot compute bit-identical values
+// from the same inputs with the same instructions, so the repeated stores are
+// benign; no block reads pnew during the launch (it is the other direction
+// buffer).  Storing only from the owning block cost more in predicate
+// arithmetic than the repeated stores cost in bandwidth.
 // Requests (registers; clamped addresses) and updates in separate phases,
 // like tile_request and tile_store.
 template <class K, typename T>
@@ -283,19 +285,15 @@ template <class K, typename T>
 __device__ __forceinline__ void tile_store_pu(const MeshK<T> &m, const Slab &s,
                                               const int64_t *s_row, const PUpd<T> &pu,
                                               const PuReq<K, T> &q, T beta, bool mask, T *tile) {
-  constexpr int n = K::n, P = K::Dm::P, TX = K::TX;
   const int xe = m.Nx - s.x0;
   const bool chk = mask && s.bnd;
-  const bool top_y = s.ey == m.ny - 1, top_z = s.ez == m.nz - 1;
   T *__restrict__ pn = pu.pnew;
   tile_for_all<K>([&](int k, int idx, int rr, int x) {
     if (idx >= K::TILE) return;
     T val = T(0);
     if (x < xe) {
       val = q.r[k] * q.d[k] + beta * q.p[k];
-      const int b = rr % n, c = (rr / n) % n;
-      if ((x < TX - 1 || x == xe - 1) && (b < P || top_y) && (c < P || top_z))
-        pn[s_row[rr] + x] = val;
+      pn[s_row[rr] + x] = val;
       if (chk && tile_constrained<K>(m, s, rr, x)) val = T(0);
     }
     tile[idx] = val;

@@ -13,7 +13,8 @@ int launch_force(int P, const MeshK<T> &m, const double *mu, const double *lam, 
                  T *state, int mask, hipStream_t st);
 // Search-direction update fused into the PCG operator: while gathering its
 // input the operator forms p = r * dinv + beta * v (v = the previous p) and
-// stores p to pnew (every slot once, by the block that owns it).
+// stores p to pnew (from every block whose tile holds the slot: identical
+// values).
 template <typename T>
 struct PUpd {
   const T *r;
