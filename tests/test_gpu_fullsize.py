@@ -9,12 +9,16 @@ every element that touches the sampled element's slots, and the outputs are
 compared on all slots of the sampled elements.  Tolerances as for the small
 meshes: 1e-5 (FP32) and 1e-12 (FP64), relative in the max norm over the
 sample; for the internal force of the near-equilibrium state the FP64 bound is
-relative to the sum of absolute element contributions."""
+relative to the sum of absolute element contributions.  The PCG operator with
+the fused direction update (the kernel the benchmark times) is checked through
+two iterations of the mixed-precision PCG against the oracle's FP64 CG on the
+whole mesh."""
 import numpy as np
 import pytest
 
 from paper_2104_13466_amd import inputs
 from paper_2104_13466_amd.sdme import FP32, FP64, MASK_BC, Context
+from oracle import solvers as osv
 from tests.gpu_setup import relerr
 from tests.oracle_setup import make
 
@@ -156,3 +160,30 @@ def test_fullsize_fp64_force_and_tangent(full):
     got, ref, _ = full.sample(full.host(y),
                               lambda pb, u, v, m: pb.mesh.tangent_apply(pb.mu, pb.lam, u, v))
     assert relerr(got, ref) < TOL64
+
+
+def test_fullsize_mixed_pcg_fused_operator(full):
+    # Two iterations of the mixed-precision PCG from x = 0: both run the FP32
+    # operator with the fused direction update, and x2 = a0 z0 + a1 (z1 + b0 z0)
+    # with z1 = D^-1 (r0 - a0 A z0) depends on every entry of the first
+    # operator output.  The oracle runs the same two FP64 CG iterations on the
+    # whole mesh (direct element loops).
+    t = full.torch
+    w = full.w
+    G = np.zeros((3, 3))
+    G[2, 2] = -0.2
+    amp = 1e-3 * min(full.L[i] / full.n[i] for i in range(3))
+    u = full.ctx.affine_field([0, 0, 0], G) + full.mask * inputs.random_coeffs(
+        w["seed"], full.n, full.P, amp)
+    b = full.mask * inputs.uniform(w["seed"], full.N, -1, 1, stream=5)
+    x = t.zeros(full.N, dtype=t.float64, device="cuda")
+    st = full.ctx.jacobi_pcg(full.mat, FP32, full.dev(b, t.float64), x,
+                             u_lin=full.dev(u, t.float64), rtol=1e-30, maxit=2, inner_rtol=1e-30,
+                             check=False)
+    assert st["iterations"] == 2
+    pb, _ = make(full.n, full.L, full.P, kind=w["kind"], E=w["E"], nu=w["nu"],
+                 dirichlet=w["dirichlet"])
+    assert np.array_equal(pb.mask, full.mask)
+    xr, its, _ = osv.pcg(pb.A(u, 0.0), b, pb.diag(u, 0.0), 1e-30, 2)
+    assert its == 2
+    assert relerr(full.host(x), xr) < TOL32
