@@ -529,8 +529,8 @@ def main():
     ap.add_argument("--steps-explicit", type=int, default=2000)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the multi-GPU path (slab partition + halo "
-              "exchange over RCCL) is not part of this build", file=sys.stderr)
+        print("bench.py runs on one GPU only: libsdme has no multi-GPU path (slab partition "
+              "+ halo exchange over RCCL is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 

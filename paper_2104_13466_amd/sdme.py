@@ -104,8 +104,8 @@ def _lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("libsdme.so is not built (run __graft_entry__.build() or "
-                              "python -m paper_2104_13466_amd.build)")
+            raise ImportError("libsdme.so is not built (run python -m "
+                              "paper_2104_13466_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             f = getattr(L, name)
