@@ -213,6 +213,43 @@ typedef struct {
 int sdme_penalty_plane(sdme_ctx *ctx, const sdme_contact *c, const double *u, double *f,
                        double *energy_host, void *stream);
 
+/* ------------------------------------------- loads given at quadrature points
+ * For the fabricated-solution problems of Section 5 (body force and boundary
+ * tractions computed from a prescribed displacement field; their work enters
+ * the virtual-work statement of Section 3 with the reference-configuration
+ * volume and face measures).
+ *
+ * sdme_quadrature_points -- physical coordinates of the quadrature points,
+ * written to host_out (host double, no device access): face = -1: the volume
+ * Gauss points, [3][E][Q^3] with q = q1 + Q (q2 + Q q3) and element
+ * e = (ez ny + ey) nx + ex; face = 0..5: the face Gauss points of the face
+ * rule (P+1 points per direction), [3][nfe][(P+1)^2] with face element
+ * fe = j ne1 + i and point p = pj (P+1) + pi, where (i, pi) run along the
+ * face's first tangential direction (y for faces 0, 1; x otherwise) and
+ * (j, pj) along the second (z for faces 0..3; y for faces 4, 5); nfe =
+ * ne1 * ne2.  Errors: SDME_EINVAL. */
+int sdme_quadrature_points(const sdme_ctx *ctx, int face, double *host_out);
+
+/* sdme_body_load -- f += sum_e sum_q w_q detJ N_a(X_q) b(X_q) for every slot
+ * a: b dev double [3][E][Q^3] (body force per unit reference volume at the
+ * volume Gauss points, layout of sdme_quadrature_points), f dev double
+ * [3][Nn], accumulated (atomics; not masked).  Errors: SDME_EINVAL. */
+int sdme_body_load(sdme_ctx *ctx, const double *b, double *f, void *stream);
+
+/* sdme_face_load -- f += int_face N_a t dA with t dev double [3][nfe][(P+1)^2]
+ * (traction per unit reference area at the face Gauss points, layout of
+ * sdme_quadrature_points).  Accumulated, not masked.  Errors: SDME_EINVAL. */
+int sdme_face_load(sdme_ctx *ctx, int face, const double *t, double *f, void *stream);
+
+/* sdme_l2_error -- host_out[c] = ( sum_e sum_q w_q detJ (u_h,c(X_q) -
+ * g_c(X_q))^2 )^(1/2) for c = 0, 1, 2: the L2 norm over the box of the
+ * difference between the field with coefficients u (dev double [3][Nn]) and
+ * the values g (dev double [3][E][Q^3] at the volume Gauss points), by the
+ * volume Gauss rule (Q = P+2).  Deterministic (block partials summed in block
+ * order).  Synchronises.  Errors: SDME_EINVAL, SDME_EDEVICE. */
+int sdme_l2_error(sdme_ctx *ctx, const double *u, const double *g, double *host_out,
+                  void *stream);
+
 /* Sensitivity of R to the element Lame parameters contracted with w:
  * g_mu[e] += scale * sum_q w_q detJ (F - F^-T) : grad w,
  * g_lam[e] += scale * sum_q w_q detJ lnJ F^-T : grad w  (dev double[E]). */

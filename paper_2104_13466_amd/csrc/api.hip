@@ -744,6 +744,72 @@ extern "C" int sdme_penalty_plane(sdme_ctx *c, const sdme_contact *ct, const dou
   return SDME_OK;
 }
 
+extern "C" int sdme_quadrature_points(const sdme_ctx *c, int face, double *o) {
+  if (!c || !o || face < -1 || face > 5) return SDME_EINVAL;
+  const sdme_mesh_desc &d = c->d;
+  const int ne[3] = {d.nx, d.ny, d.nz};
+  if (face < 0) {
+    const int Q = c->Q, Q3 = Q * Q * Q;
+    std::vector<double> x(Q), w(Q);
+    sdme::gauss_legendre(Q, x.data(), w.data());
+    for (int64_t e = 0; e < c->E; e++) {
+      const int ei[3] = {(int)(e % d.nx), (int)((e / d.nx) % d.ny), (int)(e / ((int64_t)d.nx * d.ny))};
+      for (int q = 0; q < Q3; q++) {
+        const int qi[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
+        for (int k = 0; k < 3; k++)
+          o[((size_t)k * c->E + e) * Q3 + q] =
+              d.origin[k] + d.h[k] * (ei[k] + 0.5 * (1.0 + x[qi[k]]));
+      }
+    }
+    return SDME_OK;
+  }
+  const int dir = face / 2, side = face % 2, t1 = dir == 0 ? 1 : 0, t2 = dir == 2 ? 1 : 2;
+  const int nq = c->P + 1, nfe = ne[t1] * ne[t2];
+  std::vector<double> x(nq), w(nq);
+  sdme::gauss_legendre(nq, x.data(), w.data());
+  for (int fe = 0; fe < nfe; fe++) {
+    const int i = fe % ne[t1], j = fe / ne[t1];
+    for (int p = 0; p < nq * nq; p++) {
+      const int pi = p % nq, pj = p / nq;
+      double X[3];
+      X[dir] = d.origin[dir] + (side ? ne[dir] * d.h[dir] : 0.0);
+      X[t1] = d.origin[t1] + d.h[t1] * (i + 0.5 * (1.0 + x[pi]));
+      X[t2] = d.origin[t2] + d.h[t2] * (j + 0.5 * (1.0 + x[pj]));
+      for (int k = 0; k < 3; k++) o[((size_t)k * nfe + fe) * nq * nq + p] = X[k];
+    }
+  }
+  return SDME_OK;
+}
+
+extern "C" int sdme_body_load(sdme_ctx *c, const double *b, double *f, void *stream) {
+  if (!c || !b || !f) return SDME_EINVAL;
+  if (int rc_ = ensure_device(c)) return rc_;
+  return lerr(launch_body_load(c->P, c->m64, b, f, S(stream)));
+}
+
+extern "C" int sdme_face_load(sdme_ctx *c, int face, const double *t, double *f, void *stream) {
+  if (!c || !t || !f || face < 0 || face > 5) return SDME_EINVAL;
+  if (int rc_ = ensure_device(c)) return rc_;
+  return lerr(launch_face_load(c->P, c->m64, face, t, f, S(stream)));
+}
+
+extern "C" int sdme_l2_error(sdme_ctx *c, const double *u, const double *g, double *out,
+                             void *stream) {
+  if (!c || !u || !g || !out) return SDME_EINVAL;
+  if (int rc_ = ensure_device(c)) return rc_;
+  hipStream_t st = S(stream);
+  // 3 partials per block: at most VEC_BLOCKS blocks (the partials buffer
+  // holds at least 4 VEC_BLOCKS doubles)
+  if (launch_l2_error(c->P, c->m64, u, g, c->partials, VEC_BLOCKS, c->results + 13, st))
+    return SDME_EDEVICE;
+  if (hipMemcpyAsync(c->h_res, c->results + 13, 3 * sizeof(double), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SDME_EDEVICE;
+  for (int k = 0; k < 3; k++) out[k] = std::sqrt(c->h_res[k]);
+  return SDME_OK;
+}
+
 extern "C" int sdme_material_grad_accumulate(sdme_ctx *c, const double *u, const double *w,
                                              double scale, double *gm, double *gl, void *stream) {
   if (!c || !u || !w || !gm || !gl || !std::isfinite(scale)) return SDME_EINVAL;

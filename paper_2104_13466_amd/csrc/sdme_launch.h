@@ -48,6 +48,17 @@ int launch_face(int P, const MeshK<double> &m, int mode, int face, const double 
                 int do_red, hipStream_t st);
 int face_blocks(const MeshK<double> &m, int face);
 
+// ------------------------------------------------- loads at quadrature points
+// f += int N b dV with b at the volume Gauss points [3][E][Q^3]
+int launch_body_load(int P, const MeshK<double> &m, const double *b, double *f, hipStream_t st);
+// f += int_face N t dA with t at the face Gauss points [3][nfe][(P+1)^2]
+int launch_face_load(int P, const MeshK<double> &m, int face, const double *t, double *f,
+                     hipStream_t st);
+// out[c] = sum_e sum_q w detJ (u_h - g)^2 at the volume Gauss points; partials
+// of 3 doubles per block, at most max_blocks blocks
+int launch_l2_error(int P, const MeshK<double> &m, const double *u, const double *g,
+                    double *partials, int max_blocks, double *out, hipStream_t st);
+
 // ------------------------------------------------------------ vector kernels
 // PCG scalars living in device memory (all double).
 struct PcgDev {

@@ -78,6 +78,10 @@ SIGNATURES = {
     "sdme_strain_energy": ([_vp, ctypes.POINTER(Material), _vp, _dp, _vp], _i),
     "sdme_face_traction": ([_vp, _i, _dp, _d, _vp, _vp], _i),
     "sdme_penalty_plane": ([_vp, ctypes.POINTER(Contact), _vp, _vp, _dp, _vp], _i),
+    "sdme_quadrature_points": ([_vp, _i, _dp], _i),
+    "sdme_body_load": ([_vp, _vp, _vp, _vp], _i),
+    "sdme_face_load": ([_vp, _i, _vp, _vp, _vp], _i),
+    "sdme_l2_error": ([_vp, _vp, _vp, _dp, _vp], _i),
     "sdme_material_grad_accumulate": ([_vp, _vp, _vp, _d, _vp, _vp, _vp], _i),
     "sdme_workspace_bytes": ([_vp, _i, _i, ctypes.POINTER(_sz)], _i),
     "sdme_jacobi_pcg": ([_vp, ctypes.POINTER(Material), _i, _vp, _d, _i, _vp, _vp, _d, _i, _d,
@@ -285,6 +289,39 @@ class Context:
                                        ctypes.byref(e) if energy else None, _stream(stream)),
              "penalty_plane")
         return e.value if energy else None
+
+    # ------------------------------------------ loads at quadrature points
+    def face_elements(self, face):
+        """Number of element faces on box face `face` (0..5)."""
+        d = face // 2
+        t1, t2 = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+        return self.n[t1] * self.n[t2]
+
+    def quadrature_points(self, face=-1):
+        """Coordinates of the volume Gauss points, shape (3, E, Q^3) (face = -1),
+        or of the face Gauss points of face 0..5, shape (3, nfe, (P+1)^2)."""
+        if face < 0:
+            shape = (3, self.E, self.Q ** 3)
+        else:
+            shape = (3, self.face_elements(face), (self.P + 1) ** 2)
+        out = np.zeros(shape)
+        _chk(self.L.sdme_quadrature_points(self.handle, face, _hp(out)), "quadrature_points")
+        return out
+
+    def body_load(self, b, f, stream=None):
+        _chk(self.L.sdme_body_load(self.handle, _ptr(b), _ptr(f), _stream(stream)), "body_load")
+
+    def face_load(self, face, t, f, stream=None):
+        _chk(self.L.sdme_face_load(self.handle, face, _ptr(t), _ptr(f), _stream(stream)),
+             "face_load")
+
+    def l2_error(self, u, g, stream=None):
+        """L2 norms over the box of (u_h - g) per component; g at the volume
+        Gauss points (3, E, Q^3)."""
+        out = np.zeros(3)
+        _chk(self.L.sdme_l2_error(self.handle, _ptr(u), _ptr(g), _hp(out), _stream(stream)),
+             "l2_error")
+        return out
 
     def material_grad_accumulate(self, u, w, scale, g_mu, g_lam, stream=None):
         _chk(self.L.sdme_material_grad_accumulate(self.handle, _ptr(u), _ptr(w), scale, _ptr(g_mu),
