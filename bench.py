@@ -506,6 +506,59 @@ def case_adjoint(a):
             "rel_diff": abs(ad - fd) / abs(fd)}
 
 
+def _golden(name):
+    rows = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        if line.strip() and not line.startswith("#"):
+            v = line.split()
+            rows[int(v[0])] = [float(x) for x in v[1:]]
+    return rows
+
+
+def case_static(a):
+    """Static large-strain fabricated solution of Section 5.1 (u_x = 1.9 sin x
+    - x on the 2x2x2 unit cube, x = 0 clamped, tractions of the exact field on
+    the other faces, body force -Div P): Newton from u = 0 to 1e-8 with
+    Jacobi-PCG to 1e-8, P = 2, 4, 6, 8, for the modal (ST), SDME-M and SDME-H
+    bases in FP64 and SDME-H mixed; L2 errors, Newton and PCG iterations and
+    time per Newton iteration beside the paper's printed values (Tables
+    Tab:Static_error, Tab:NH_average_IT_CGD, Tab:NH_average_Time_CGD)."""
+    import torch
+
+    from paper_2104_13466_amd import fabricated as pf
+    from paper_2104_13466_amd.sdme import FP32, FP64, Context
+    l2 = _golden("static_l2_errors.txt")
+    its = _golden("static_cgd_iterations.txt")
+    rows = []
+    for P in (2, 4, 6, 8):
+        for kind, prec in ((1, FP64), (2, FP64), (4, FP64), (4, FP32)):
+            ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=kind, dirichlet=pf.DIRICHLET_X0)
+            lam, mu = pf.lame()
+            mat = Context.material(torch.full((ctx.E,), mu, dtype=torch.float64, device="cuda"),
+                                   torch.full((ctx.E,), lam, dtype=torch.float64, device="cuda"),
+                                   1.0)
+            f = torch.zeros(3 * ctx.Nn, dtype=torch.float64, device="cuda")
+            pf.static_loads(ctx, f)
+            g = pf.static_exact_at_gauss_points(ctx)
+            u = torch.zeros_like(f)
+            ctx.newton_static(mat, prec, u.clone(), f_ext=f)  # warm-up
+            st, ms = timed(lambda: ctx.newton_static(mat, prec, u, f_ext=f, newton_rtol=1e-8,
+                                                     pcg_rtol=1e-8, max_pcg=20000))
+            err = ctx.l2_error(u, g)
+            col = {1: 0, 2: 1, 4: 2}[kind]
+            row = {"P": P, "basis": KIND_NAMES[kind], "prec": "fp64" if prec == FP64 else "mixed",
+                   "dofs_free": int(l2[P][0]), "l2_error": [float("%.4g" % e) for e in err],
+                   "paper_l2_error": l2[P][1:], "newton": st["newton"],
+                   "pcg_per_newton": round(st["iterations"] / max(st["newton"], 1), 1),
+                   "paper_cgd_per_newton": its[P][1 + col],
+                   "ms_per_newton": round(ms / max(st["newton"], 1), 3),
+                   "paper_cgd_s_per_newton": its[P][4 + col]}
+            log("static %s" % row)
+            rows.append(row)
+            ctx.close()
+    return {"case": "static", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -524,7 +577,8 @@ def main():
                     help="only the per-operator launches, 12 mixed PCG iterations and a 1 GiB "
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params"],
+    ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params",
+                                      "static"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
     a = ap.parse_args()
@@ -538,7 +592,7 @@ def main():
 
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
-              "adjoint": case_adjoint, "params": case_params}[a.case]
+              "adjoint": case_adjoint, "params": case_params, "static": case_static}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)

@@ -129,3 +129,19 @@ def test_static_example_basis_independent_p4():
     errs = [static_solve(4, kind, FP64)[2] for kind in (ob.SDME_H, ob.SDME_M, ob.MODAL, ob.NODAL)]
     for e in errs[1:]:
         assert relerr(e, errs[0]) < 1e-5
+
+
+def _pcg_per_newton(P, kind):
+    _, st, _, _ = static_solve(P, kind, FP64)
+    return st["iterations"] / st["newton"]
+
+
+def test_static_example_iteration_trend_matches_paper():
+    # Table Tab:NH_average_IT_CGD: the standard modal basis needs 3.7x (P=4) and
+    # 7.9x (P=8) the CGD iterations of SDME-M, and SDME-H needs fewer than
+    # SDME-M at P = 4
+    r = {P: {k: _pcg_per_newton(P, k) for k in (ob.MODAL, ob.SDME_M, ob.SDME_H)} for P in (4, 8)}
+    for P in (4, 8):
+        assert r[P][ob.MODAL] >= 3.0 * r[P][ob.SDME_M]
+    assert r[8][ob.MODAL] / r[8][ob.SDME_M] > r[4][ob.MODAL] / r[4][ob.SDME_M]
+    assert r[4][ob.SDME_H] < r[4][ob.SDME_M]
