@@ -220,3 +220,87 @@ def static_solve(P, kind, pcg_rtol=1e-10, max_pcg=5000):
                                 max_pcg=max_pcg)
     err = l2_error(mesh, u, static_field(volume_points(mesh)))
     return u, hist, err
+
+
+# ---------------------------------------- transient example (Sec. 5.2, wave)
+RHO_WAVE = 1.0
+
+
+def wave_field(X, t):
+    """u* = (sin(pi x / 2) sin(2 pi t), 0, 0) (Eq. eq:large_field)."""
+    out = np.zeros_like(X)
+    out[0] = np.sin(0.5 * np.pi * X[0]) * np.sin(2.0 * np.pi * t)
+    return out
+
+
+_D2 = ((-2, -1.0 / 12), (-1, 16.0 / 12), (0, -30.0 / 12), (1, 16.0 / 12), (2, -1.0 / 12))
+
+
+def time_derivative(ufun_t, X, t, order, tau=1e-3):
+    """First or second derivative in t of ufun_t(X, t), fourth-order central
+    differences."""
+    st = _D4 if order == 1 else _D2
+    out = np.zeros_like(X)
+    for k, c in st:
+        out += c * ufun_t(X, t + k * tau)
+    return out / (tau if order == 1 else tau * tau)
+
+
+def dynamic_body_force(ufun_t, X, t, lam, mu, rho, delta=1e-3):
+    """b = rho d2u*/dt2 - Div P(F(u*)) at points X (3, N) and time t."""
+    return (rho * time_derivative(ufun_t, X, t, 2) +
+            body_force(lambda Y: ufun_t(Y, t), X, lam, mu, delta))
+
+
+def wave_loads(mesh, Bf, t):
+    lam, mu = lame(E_STATIC, NU_STATIC)
+    Xv = volume_points(mesh)
+    bv = dynamic_body_force(wave_field, Xv.reshape(3, -1), t, lam, mu, RHO_WAVE)
+    f = body_load(mesh, bv.reshape(Xv.shape))
+    for face in range(1, 6):
+        Xf = face_points(mesh, face)
+        tf = traction(lambda Y: wave_field(Y, t), face, Xf.reshape(3, -1), lam, mu)
+        f += face_load(mesh, face, Bf, tf.reshape(Xf.shape))
+    return f
+
+
+def _wave_problem(P, kind):
+    mesh, Bf = static_mesh(P, kind)
+    lam, mu = lame(E_STATIC, NU_STATIC)
+    mask = osv.dirichlet_mask(mesh, 0o7)
+    pb = osv.Problem(mesh, np.full(mesh.E, mu), np.full(mesh.E, lam), RHO_WAVE, mask)
+    Xv = volume_points(mesh)
+    vq = time_derivative(wave_field, Xv, 0.0, 1)
+    # the initial velocity: L2 projection of du*/dt(0) (rho M v0 = rho int N v*)
+    v0, _ = pb.mass_solve(RHO_WAVE * body_load(mesh, vq), 1e-13)
+    return mesh, Bf, pb, v0
+
+
+def wave_explicit(P, kind, dt, nsteps, mass_rtol=1e-12):
+    """Central differences (start step of Section 4) from u = 0 and the
+    projected initial velocity; returns (u_nsteps, L2 errors at t = nsteps dt)."""
+    mesh, Bf, pb, v0 = _wave_problem(P, kind)
+    u_cur = np.zeros(3 * mesh.Nn)
+    u_prev = osv.explicit_start(pb, u_cur, v0, wave_loads(mesh, Bf, 0.0), dt, mass_rtol)
+    for n in range(nsteps):
+        f = wave_loads(mesh, Bf, n * dt) if n else wave_loads(mesh, Bf, 0.0)
+        u_prev, u_cur = u_cur, osv.explicit_step(pb, u_prev, u_cur, f, dt, mass_rtol)
+    err = l2_error(mesh, u_cur, wave_field(volume_points(mesh), nsteps * dt))
+    return u_cur, err
+
+
+def wave_newmark(P, kind, dt, nsteps, newton_rtol=1e-8, pcg_rtol=1e-8):
+    """Newmark (beta = 1/4, gamma = 1/2) with Newton from u = 0, the projected
+    initial velocity and a_0 = M^-1 (f_0 - R(0)); returns (u, L2 errors,
+    Newton iterations, PCG iterations per step)."""
+    mesh, Bf, pb, v = _wave_problem(P, kind)
+    u = np.zeros(3 * mesh.Nn)
+    a, _ = pb.mass_solve(wave_loads(mesh, Bf, 0.0) - pb.R(u), 1e-13)
+    newton, pcg_its = 0, []
+    for n in range(nsteps):
+        u, v, a, nk, its = osv.newmark_step(pb, u, v, a, wave_loads(mesh, Bf, (n + 1) * dt), dt,
+                                            newton_rtol, pcg_rtol)
+        newton += nk
+        pcg_its += its
+    err = l2_error(mesh, u, wave_field(volume_points(mesh), nsteps * dt))
+    return u, err, newton, pcg_its

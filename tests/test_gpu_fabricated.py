@@ -145,3 +145,83 @@ def test_static_example_iteration_trend_matches_paper():
         assert r[P][ob.MODAL] >= 3.0 * r[P][ob.SDME_M]
     assert r[8][ob.MODAL] / r[8][ob.SDME_M] > r[4][ob.MODAL] / r[4][ob.SDME_M]
     assert r[4][ob.SDME_H] < r[4][ob.SDME_M]
+
+
+# ----------------------------------------- transient example, Section 5.2
+from tests.test_oracle_fabricated import (WAVE_DT_EXPLICIT, WAVE_DT_NEWMARK,  # noqa: E402
+                                          WAVE_STEPS_EXPLICIT, WAVE_STEPS_NEWMARK, paper_wave_l2)
+
+
+def wave_ctx(P, kind):
+    import torch
+    ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=kind, dirichlet=pf.DIRICHLET_X0)
+    lam, mu = pf.lame()
+    mat = Context.material(torch.full((ctx.E,), mu, dtype=torch.float64, device="cuda"),
+                           torch.full((ctx.E,), lam, dtype=torch.float64, device="cuda"), pf.RHO)
+    return ctx, mat
+
+
+def check_paper(P, err, ref):
+    # u_x within 1.5x; the lateral components within 2x (the paper's u_y and
+    # u_z differ by up to 10 % from each other although the problem is
+    # symmetric in y and z, so its lateral errors carry some asymmetry of its
+    # set-up); from P = 6 on, the printed errors are a floor the solution
+    # here stays below
+    if P <= 4:
+        assert within_factor(err[0], ref[0], 1.5), (err, ref)
+        assert within_factor(err[1:], ref[1:], 2.0), (err, ref)
+    else:
+        assert np.all(err <= 1.5 * np.asarray(ref)), (err, ref)
+
+
+# the modal basis needs ~1300 mass-PCG iterations per explicit step at P = 4:
+# it is run at P = 2 only
+@pytest.mark.parametrize("P,kind", [(2, ob.MODAL), (2, ob.SDME_M), (4, ob.SDME_M), (6, ob.SDME_M)],
+                         ids=["P2-modal", "P2-sdme_m", "P4-sdme_m", "P6-sdme_m"])
+def test_wave_explicit_matches_paper(P, kind):
+    ctx, mat = wave_ctx(P, kind)
+    u, mass_its = pf.wave_explicit(ctx, mat, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, FP64)
+    err = ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "wave", 0.25))
+    ref = paper_wave_l2()[("explicit", ob.KIND_NAMES[kind].replace("-", "_"), P)]
+    print("explicit P=%d %s L2 %s paper %s mass its/step %.1f" % (
+        P, ob.KIND_NAMES[kind], err, ref, mass_its / WAVE_STEPS_EXPLICIT))
+    check_paper(P, err, ref)
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "mixed"])
+def test_wave_newmark_matches_paper(P, prec):
+    ctx, mat = wave_ctx(P, ob.SDME_H)
+    u, newton, pcg = pf.wave_newmark(ctx, mat, WAVE_DT_NEWMARK, WAVE_STEPS_NEWMARK, prec)
+    err = ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "wave", 0.25))
+    ref = paper_wave_l2()[("newmark", "sdme_h", P)]
+    print("newmark P=%d L2 %s paper %s newton %d pcg/solve %.1f" % (P, err, ref, newton,
+                                                                   pcg / newton))
+    check_paper(P, err, ref)
+
+
+def test_wave_explicit_matches_oracle_p2():
+    ctx, mat = wave_ctx(2, ob.SDME_M)
+    u, _ = pf.wave_explicit(ctx, mat, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, FP64)
+    uo, erro = fb.wave_explicit(2, ob.SDME_M, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT)
+    assert relerr(u.cpu().numpy(), uo) < 1e-7
+
+
+def test_wave_newmark_matches_oracle_p2():
+    ctx, mat = wave_ctx(2, ob.SDME_H)
+    u, newton, _ = pf.wave_newmark(ctx, mat, WAVE_DT_NEWMARK, WAVE_STEPS_NEWMARK, FP64)
+    uo, erro, newton_o, _ = fb.wave_newmark(2, ob.SDME_H, WAVE_DT_NEWMARK, WAVE_STEPS_NEWMARK)
+    assert relerr(u.cpu().numpy(), uo) < 1e-7
+    assert abs(newton - newton_o) <= max(1, 0.02 * newton_o)
+
+
+def test_wave_newmark_iteration_trend_matches_paper():
+    # Table Tab:TransientNmk_NH_NIT_Hexa: ST needs 18x the CGD iterations of
+    # SDME-M and SDME-H at P = 4
+    its = {}
+    for kind in (ob.MODAL, ob.SDME_M, ob.SDME_H):
+        ctx, mat = wave_ctx(4, kind)
+        _, newton, pcg = pf.wave_newmark(ctx, mat, WAVE_DT_NEWMARK, 25, FP64)
+        its[kind] = pcg / newton
+    assert its[ob.MODAL] >= 5.0 * its[ob.SDME_M]
+    assert its[ob.MODAL] >= 5.0 * its[ob.SDME_H]

@@ -132,3 +132,30 @@ def test_l2_error_zero_on_represented_fields_and_constant_offset():
     assert np.abs(fb.l2_error(mesh, u, g)).max() <= 1e-13
     err = fb.l2_error(mesh, u, g + np.array([1.0, 2.0, 0.0])[:, None, None])
     assert np.allclose(err, [1.0, 2.0, 0.0], rtol=1e-13, atol=1e-13)  # |box| = 1
+
+
+GOLDEN_WAVE = os.path.join(os.path.dirname(__file__), "golden", "wave_l2_errors.txt")
+WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT = 0.25 / 800, 800
+WAVE_DT_NEWMARK, WAVE_STEPS_NEWMARK = 2e-3, 125
+
+
+def paper_wave_l2():
+    out = {}
+    for line in open(GOLDEN_WAVE):
+        if line.strip() and not line.startswith("#"):
+            scheme, basis, P, dofs, ux, uy, uz = line.split()
+            out[(scheme, basis, int(P))] = (float(ux), float(uy), float(uz))
+    return out
+
+
+def test_wave_explicit_reproduces_paper_l2_errors_p2():
+    # Table Tab:Transient_NH_L2errorHexa_SDME_M at P = 2; 800 steps to t = 0.25
+    _, err = fb.wave_explicit(2, ob.SDME_M, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT)
+    assert within_factor(err, paper_wave_l2()[("explicit", "sdme_m", 2)], 1.25), err
+
+
+def test_wave_newmark_reproduces_paper_l2_errors_p2():
+    # Table Tab:TransientNmk_NH_L2errorHexa_SDME_H at P = 2, dt = 2e-3
+    _, err, newton, its = fb.wave_newmark(2, ob.SDME_H, WAVE_DT_NEWMARK, WAVE_STEPS_NEWMARK)
+    assert within_factor(err, paper_wave_l2()[("newmark", "sdme_h", 2)], 1.25), err
+    assert newton >= WAVE_STEPS_NEWMARK
