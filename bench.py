@@ -559,6 +559,60 @@ def case_static(a):
     return {"case": "static", "rows": rows}
 
 
+def case_wave(a):
+    """Transient fabricated solution of Section 5.2 (u_x = sin(pi x / 2)
+    sin(2 pi t) on the 2x2x2 unit cube to t = 0.25, x = 0 clamped):
+    central differences (800 steps) and Newmark (dt = 2e-3, 125 steps, Newton
+    and Jacobi-PCG to 1e-8), P = 2, 4, 6; L2 errors, iterations and times
+    beside the paper's tables (Tab:Transient_NH_L2errorHexa_ST, _SDME_M,
+    Tab:TransientNmk_NH_L2errorHexa_SDME_H, Tab:TransientNmk_NH_NIT_Hexa,
+    Tab:TransientNmk_NH_time_Hexa)."""
+    import torch
+
+    from paper_2104_13466_amd import fabricated as pf
+    from paper_2104_13466_amd.sdme import FP32, FP64, Context
+    ref = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "wave_l2_errors.txt")):
+        if line.strip() and not line.startswith("#"):
+            v = line.split()
+            ref[(v[0], v[1], int(v[2]))] = [float(x) for x in v[4:]]
+    nit = _golden("wave_newmark_cgd_iterations.txt")
+
+    def mk(P, kind):
+        ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=kind, dirichlet=pf.DIRICHLET_X0)
+        lam, mu = pf.lame()
+        mat = Context.material(torch.full((ctx.E,), mu, dtype=torch.float64, device="cuda"),
+                               torch.full((ctx.E,), lam, dtype=torch.float64, device="cuda"), pf.RHO)
+        return ctx, mat
+
+    rows = []
+    for P in (2, 4, 6):
+        runs = [("explicit", 2, FP64), ("explicit", 2, FP32), ("newmark", 4, FP64),
+                ("newmark", 4, FP32), ("newmark", 2, FP64), ("newmark", 1, FP64)]
+        if P <= 4:
+            runs.append(("explicit", 1, FP64))
+        for scheme, kind, prec in runs:
+            ctx, mat = mk(P, kind)
+            if scheme == "explicit":
+                (u, its), ms = timed(lambda: pf.wave_explicit(ctx, mat, 0.25 / 800, 800, prec))
+                row = {"steps": 800, "mass_pcg_per_step": round(its / 800, 1),
+                       "ms_per_step": round(ms / 800, 3), "force_prec": "fp64" if prec == FP64 else "fp32"}
+            else:
+                (u, newton, pcg), ms = timed(lambda: pf.wave_newmark(ctx, mat, 2e-3, 125, prec))
+                col = {1: 0, 2: 1, 4: 2}[kind]
+                row = {"steps": 125, "newton": newton, "pcg_per_solve": round(pcg / newton, 2),
+                       "paper_cgd_per_solve": nit[P][col], "ms_per_step": round(ms / 125, 3),
+                       "prec": "fp64" if prec == FP64 else "mixed"}
+            err = ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "wave", 0.25))
+            row.update({"scheme": scheme, "P": P, "basis": KIND_NAMES[kind],
+                        "l2_error": [float("%.4g" % e) for e in err],
+                        "paper_l2_error": ref.get((scheme, KIND_NAMES[kind], P))})
+            log("wave %s" % row)
+            rows.append(row)
+            ctx.close()
+    return {"case": "wave", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -578,7 +632,7 @@ def main():
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params",
-                                      "static"],
+                                      "static", "wave"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
     a = ap.parse_args()
@@ -592,7 +646,8 @@ def main():
 
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
-              "adjoint": case_adjoint, "params": case_params, "static": case_static}[a.case]
+              "adjoint": case_adjoint, "params": case_params, "static": case_static,
+              "wave": case_wave}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)
