@@ -102,13 +102,22 @@ typedef struct sdme_ctx sdme_ctx;
 typedef struct {
   int nx, ny, nz;     /* hexahedra per direction (>= 1)                       */
   int P;              /* polynomial order, 1..8                               */
-  int Q;              /* Gauss-Legendre points per direction: must be P+2      */
+  int Q;              /* volume points per direction: P+2 (Gauss-Legendre) or  */
+                      /* P+1 (Gauss-Lobatto-Legendre; with the nodal basis    */
+                      /* collocated: diagonal mass)                           */
   int basis;          /* SDME_BASIS_*                                          */
   double k;           /* SD parameter k (Eq. Y), paper value 0.5               */
   double lambda_h;    /* SDME-H parameter lambda (Eq. EffectiveStiffness_lambda), paper 100 */
   double h[3];        /* element edge lengths (affine boxes)                   */
   double origin[3];   /* coordinates of the box corner                         */
   uint32_t dirichlet; /* bit (face*3 + comp): faces 0 x=0, 1 x=max, 2 y=0, 3 y=max, 4 z=0, 5 z=max */
+  int mass_rule;      /* 0: the mass with the volume rule (consistent);        */
+                      /* 1: the mass with the Gauss-Lobatto-Legendre rule of   */
+                      /* P+1 points (diagonal for the nodal basis: the          */
+                      /* Lagrange diagonal-mass variant of Section 5.2), used by */
+                      /* sdme_mass_apply, mass solves, explicit steps, energies */
+                      /* and sdme_lambda_max; the mass-shifted operators        */
+                      /* (mass_shift != 0, Newmark) then return SDME_EINVAL     */
 } sdme_mesh_desc;
 
 /* Create a context for a structured box mesh.  The basis is built on the
@@ -245,7 +254,7 @@ int sdme_face_load(sdme_ctx *ctx, int face, const double *t, double *f, void *st
  * g_c(X_q))^2 )^(1/2) for c = 0, 1, 2: the L2 norm over the box of the
  * difference between the field with coefficients u (dev double [3][Nn]) and
  * the values g (dev double [3][E][Q^3] at the volume Gauss points), by the
- * volume Gauss rule (Q = P+2).  Deterministic (block partials summed in block
+ * volume rule of the mesh (Q points per direction).  Deterministic (block partials summed in block
  * order).  Synchronises.  Errors: SDME_EINVAL, SDME_EDEVICE. */
 int sdme_l2_error(sdme_ctx *ctx, const double *u, const double *g, double *host_out,
                   void *stream);

@@ -56,6 +56,23 @@ def gll_points(P):
     return np.concatenate([[-1.0], r, [1.0]])
 
 
+def gll_rule(q):
+    """Gauss-Lobatto-Legendre rule of q points on [-1, 1]: the points of
+    gll_points(q - 1), weights 2 / (q (q - 1) L_{q-1}(x)^2); exact for
+    polynomials of degree 2q - 3."""
+    x = gll_points(q - 1)
+    c = np.zeros(q)
+    c[q - 1] = 1.0
+    L = _npleg.legval(x, c)
+    return x, 2.0 / (q * (q - 1) * L * L)
+
+
+def volume_rule(P, Q):
+    """The volume rule of the meshes: Gauss-Legendre for Q = P + 2 (Q points),
+    Gauss-Lobatto-Legendre for Q = P + 1 (collocated with the nodal basis)."""
+    return gll_rule(Q) if Q == P + 1 else gauss_legendre(Q)
+
+
 def jacobi(n, a, b, x):
     """Jacobi polynomial P_n^{a,b}(x) and its derivative, by the three-term
     recurrence and d/dx P_n^{a,b} = (n+a+b+1)/2 P_{n-1}^{a+1,b+1}."""
@@ -206,8 +223,9 @@ class Basis1D:
         return (self.T @ V).T, (self.T @ Dv).T
 
     def tables(self, Q):
-        """Gauss points/weights and B[q][s], D[q][s] at Q Gauss-Legendre points."""
-        x, w = gauss_legendre(Q)
+        """Points/weights of the volume rule with Q points (volume_rule) and
+        B[q][s], D[q][s] there."""
+        x, w = volume_rule(self.P, Q)
         B, D = self.eval(x)
         return x, w, B, D
 

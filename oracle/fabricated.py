@@ -32,7 +32,7 @@ def volume_points(mesh, origin=(0.0, 0.0, 0.0)):
     """(3, E, Q^3): Gauss point q = q1 + Q (q2 + Q q3) of element
     e = (ez ny + ey) nx + ex at X_d = origin_d + h_d (e_d + (1 + x_{q_d}) / 2)."""
     Q = mesh.Q
-    x, _ = ob.gauss_legendre(Q)
+    x, _ = ob.volume_rule(mesh.P, Q)
     out = np.zeros((3, mesh.E, Q ** 3))
     for e in range(mesh.E):
         ei = (e % mesh.nx, (e // mesh.nx) % mesh.ny, e // (mesh.nx * mesh.ny))
@@ -187,10 +187,12 @@ def static_field(X):
     return out
 
 
-def static_mesh(P, kind, n=2):
-    """(mesh, face table Bf) of the unit cube with n^3 hexahedra."""
-    b, x, w, B, D = ob.build(P, P + 2, kind)
-    m = fem.Mesh(n, n, n, P, P + 2, np.full(3, 1.0 / n), B, D, w)
+def static_mesh(P, kind, n=2, Q=None):
+    """(mesh, face table Bf) of the unit cube with n^3 hexahedra (volume rule
+    of Q points per direction, default P + 2)."""
+    Q = P + 2 if Q is None else Q
+    b, x, w, B, D = ob.build(P, Q, kind)
+    m = fem.Mesh(n, n, n, P, Q, np.full(3, 1.0 / n), B, D, w)
     xf, _ = ob.gauss_legendre(P + 1)
     Bf, _ = b.eval(xf)
     return m, Bf
@@ -264,11 +266,18 @@ def wave_loads(mesh, Bf, t):
     return f
 
 
-def _wave_problem(P, kind):
-    mesh, Bf = static_mesh(P, kind)
+def _wave_problem(P, kind, Q=None, lumped=False):
+    """Mesh, face table, problem and projected initial velocity of the wave
+    example; lumped: the mass with the Gauss-Lobatto-Legendre rule of P+1
+    points (diagonal for the nodal basis), the rest with the mesh's rule."""
+    mesh, Bf = static_mesh(P, kind, Q=Q)
     lam, mu = lame(E_STATIC, NU_STATIC)
     mask = osv.dirichlet_mask(mesh, 0o7)
     pb = osv.Problem(mesh, np.full(mesh.E, mu), np.full(mesh.E, lam), RHO_WAVE, mask)
+    if lumped:
+        mm, _ = static_mesh(P, kind, Q=P + 1)
+        pbm = osv.Problem(mm, pb.mu, pb.lam, RHO_WAVE, mask)
+        pb.M, pb.mass_diag, pb.mass_solve = pbm.M, pbm.mass_diag, pbm.mass_solve
     Xv = volume_points(mesh)
     vq = time_derivative(wave_field, Xv, 0.0, 1)
     # the initial velocity: L2 projection of du*/dt(0) (rho M v0 = rho int N v*)
@@ -276,16 +285,20 @@ def _wave_problem(P, kind):
     return mesh, Bf, pb, v0
 
 
-def wave_explicit(P, kind, dt, nsteps, mass_rtol=1e-12):
+def wave_explicit(P, kind, dt, nsteps, mass_rtol=1e-12, Q=None, lumped=False):
     """Central differences (start step of Section 4) from u = 0 and the
-    projected initial velocity; returns (u_nsteps, L2 errors at t = nsteps dt)."""
-    mesh, Bf, pb, v0 = _wave_problem(P, kind)
+    projected initial velocity; returns (u_nsteps, L2 errors at t = nsteps dt)
+    (errors by the P + 2 point Gauss-Legendre rule)."""
+    mesh, Bf, pb, v0 = _wave_problem(P, kind, Q, lumped)
     u_cur = np.zeros(3 * mesh.Nn)
     u_prev = osv.explicit_start(pb, u_cur, v0, wave_loads(mesh, Bf, 0.0), dt, mass_rtol)
     for n in range(nsteps):
         f = wave_loads(mesh, Bf, n * dt) if n else wave_loads(mesh, Bf, 0.0)
         u_prev, u_cur = u_cur, osv.explicit_step(pb, u_prev, u_cur, f, dt, mass_rtol)
-    err = l2_error(mesh, u_cur, wave_field(volume_points(mesh), nsteps * dt))
+    # the error by the Gauss-Legendre rule of P + 2 points, whatever the
+    # rule of the run
+    emesh, _ = static_mesh(P, kind)
+    err = l2_error(emesh, u_cur, wave_field(volume_points(emesh), nsteps * dt))
     return u_cur, err
 
 

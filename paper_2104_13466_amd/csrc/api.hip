@@ -35,6 +35,13 @@ struct sdme_ctx {
   int *h_flag = nullptr;
   MeshK<double> m64;
   MeshK<float> m32;
+  // the meshes of the mass operator: the same as m64, m32, or (mass_rule 1)
+  // with the Gauss-Lobatto-Legendre rule of P+1 points and its own tables
+  MeshK<double> mm64;
+  MeshK<float> mm32;
+  double *tabm64 = nullptr;
+  float *tabm32 = nullptr;
+  std::vector<double> tabm_host;
   int device = 0;
   bool dev_ready = false;
   // optional per-launch timing of the PCG operator (HIP events on the solve
@@ -63,6 +70,12 @@ Reduce red_at(sdme_ctx *c, int slot) { return Reduce{c->partials, c->counter, c-
 
 template <typename T>
 const MeshK<T> &mk(const sdme_ctx *c);
+template <typename T>
+const MeshK<T> &mkm(const sdme_ctx *c);
+template <>
+const MeshK<double> &mkm<double>(const sdme_ctx *c) { return c->mm64; }
+template <>
+const MeshK<float> &mkm<float>(const sdme_ctx *c) { return c->mm32; }
 template <>
 const MeshK<double> &mk<double>(const sdme_ctx *c) { return c->m64; }
 template <>
@@ -129,7 +142,7 @@ struct Op {
 template <typename T>
 int apply_op(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *v, T *y, Reduce red,
              int do_red, const int *skip, hipStream_t st, const PUpd<T> *pu = nullptr) {
-  if (op.kind == 2) return launch_mass<T>(c->P, mk<T>(c), op.rho, v, y, 1, red, do_red, skip, st);
+  if (op.kind == 2) return launch_mass<T>(c->P, mkm<T>(c), op.rho, v, y, 1, red, do_red, skip, st);
   if (do_red) return -2;
   return launch_tangent<T>(c->P, mk<T>(c), mat->mu, mat->lam, op.kind == 1 ? op.ulin : nullptr,
                            op.kind == 0 ? op.state : nullptr, op.msr, v, y, 1, pu, skip, st);
@@ -294,7 +307,8 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
   Op<double> op64{mass_only ? 2 : 0, state64, nullptr, shift * mat->rho, mat->rho};
   // FP64 diagonal
   if (launch_fill<double>(w.d64, 0.0, N, st)) return SDME_EDEVICE;
-  if (launch_diag<double>(P, c->m64, mat->mu, mat->lam, mass_only ? nullptr : state64,
+  if (launch_diag<double>(P, mass_only ? c->mm64 : c->m64, mat->mu, mat->lam,
+                          mass_only ? nullptr : state64,
                           mass_only ? mat->rho : shift * mat->rho, w.d64, 1, st))
     return SDME_EDEVICE;
   if (launch_bc<double>(w.d64, 1, c->m64, st) || launch_recip(w.d64, N, st)) return SDME_EDEVICE;
@@ -353,9 +367,11 @@ static int ensure_device(sdme_ctx *c) {
   int64_t E = c->E;
   int TS = (int)c->tab_host.size();
   const std::vector<double> &tab = c->tab_host;
-  int nblk = elem_blocks(P, 4, d->nx, d->ny, d->nz);
-  int nblk8 = elem_blocks(P, 8, d->nx, d->ny, d->nz);
-  if (nblk8 > nblk) nblk = nblk8;
+  int nblk = 0;
+  for (int q : {c->Q, c->mm64.Q})
+    for (int word : {4, 8})
+      for (bool grad : {true, false})
+        nblk = std::max(nblk, elem_blocks(P, q, word, d->nx, d->ny, d->nz, grad));
   if (nblk < 2 * VEC_BLOCKS) nblk = 2 * VEC_BLOCKS;
   int64_t fb = std::max(std::max(d->nx * d->ny, d->ny * d->nz), d->nx * d->nz);
   if (fb > nblk) nblk = (int)fb;
@@ -365,6 +381,8 @@ static int ensure_device(sdme_ctx *c) {
     bytes += (b + 255) & ~(size_t)255;
     return o;
   };
+  const int TSM = (int)c->tabm_host.size();
+  size_t o_tm64 = take(sizeof(double) * TSM), o_tm32 = take(sizeof(float) * TSM);
   size_t o_t64 = take(sizeof(double) * TS), o_t32 = take(sizeof(float) * TS),
          o_flag = take(sizeof(int)), o_pcg = take(2 * sizeof(PcgDev)),
          o_part = take(sizeof(double) * 2 * (size_t)nblk), o_cnt = take(sizeof(unsigned) * 4),
@@ -373,17 +391,24 @@ static int ensure_device(sdme_ctx *c) {
     return SDME_EDEVICE;
   char *base = (char *)c->dev_block;
   c->tab64 = (double *)(base + o_t64);
+  c->tabm64 = (double *)(base + o_tm64);
+  c->tabm32 = (float *)(base + o_tm32);
   c->tab32 = (float *)(base + o_t32);
   c->flag = (int *)(base + o_flag);
   c->pcg = (PcgDev *)(base + o_pcg);
   c->partials = (double *)(base + o_part);
   c->counter = (unsigned *)(base + o_cnt);
   c->results = (double *)(base + o_res);
-  std::vector<float> tab32(TS);
+  std::vector<float> tab32(TS), tabm32(TSM);
   for (int i = 0; i < TS; i++) tab32[i] = (float)tab[i];
+  for (int i = 0; i < TSM; i++) tabm32[i] = (float)c->tabm_host[i];
   if (hipMemset(c->dev_block, 0, bytes) != hipSuccess ||
       hipMemcpy(c->tab64, tab.data(), sizeof(double) * TS, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab32, tab32.data(), sizeof(float) * TS, hipMemcpyHostToDevice) != hipSuccess ||
+      (TSM && (hipMemcpy(c->tabm64, c->tabm_host.data(), sizeof(double) * TSM,
+                         hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(c->tabm32, tabm32.data(), sizeof(float) * TSM, hipMemcpyHostToDevice) !=
+                   hipSuccess)) ||
       hipHostMalloc(&c->host_block, 4096, hipHostMallocDefault) != hipSuccess) {
     hipFree(c->dev_block);
     c->dev_block = nullptr;
@@ -396,6 +421,13 @@ static int ensure_device(sdme_ctx *c) {
   c->m64.flag = c->flag;
   c->m32.tab = c->tab32;
   c->m32.flag = c->flag;
+  c->mm64 = c->m64;
+  c->mm32 = c->m32;
+  if (TSM) {
+    c->mm64.Q = c->mm32.Q = c->P + 1;
+    c->mm64.tab = c->tabm64;
+    c->mm32.tab = c->tabm32;
+  }
   c->dev_ready = true;
   return SDME_OK;
 }
@@ -416,10 +448,42 @@ extern "C" const char *sdme_status_string(int s) {
   }
 }
 
+namespace {
+// Tables of Dims<P, Q>: B, D, W, B*B, D*D, B*D at the Q points of the volume
+// rule; Bf, Wf at the P+1 Gauss-Legendre points of the face rule.
+bool build_tables(const Basis &basis, int P, int Q, std::vector<double> &tab) {
+  const int n = P + 1;
+  tab.assign(2 * Q * n + Q + 3 * Q * n + n * n + n, 0.0);
+  std::vector<double> xq(Q), wq(Q), v(n), dv(n);
+  if (!sdme::volume_rule(P, Q, xq.data(), wq.data())) return false;
+  for (int q = 0; q < Q; q++) {
+    basis.eval(xq[q], v.data(), dv.data());
+    for (int s = 0; s < n; s++) {
+      tab[q * n + s] = v[s];
+      tab[Q * n + q * n + s] = dv[s];
+      int o = 2 * Q * n + Q;
+      tab[o + q * n + s] = v[s] * v[s];
+      tab[o + Q * n + q * n + s] = dv[s] * dv[s];
+      tab[o + 2 * Q * n + q * n + s] = v[s] * dv[s];
+    }
+    tab[2 * Q * n + q] = wq[q];
+  }
+  std::vector<double> xf(n), wf(n);
+  sdme::gauss_legendre(n, xf.data(), wf.data());
+  int of = 2 * Q * n + Q + 3 * Q * n;
+  for (int i = 0; i < n; i++) {
+    basis.eval(xf[i], v.data(), nullptr);
+    for (int s = 0; s < n; s++) tab[of + i * n + s] = v[s];
+    tab[of + n * n + i] = wf[i];
+  }
+  return true;
+}
+}  // namespace
+
 extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   if (!d || !out) return SDME_EINVAL;
   *out = nullptr;
-  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->P < 1 || d->P > 8 || d->Q != d->P + 2 ||
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->P < 1 || d->P > 8 || (d->Q != d->P + 2 && d->Q != d->P + 1) || d->mass_rule < 0 || d->mass_rule > 1 ||
       d->basis < 0 || d->basis > 4 || !(d->k >= 0 && d->k <= 1) || !(d->lambda_h >= 0) ||
       !(d->h[0] > 0 && d->h[1] > 0 && d->h[2] > 0) || (d->dirichlet >> 18) != 0)
     return SDME_EINVAL;
@@ -442,33 +506,16 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   }
   // tables: B, D, W, B*B, D*D, B*D at Q points; Bf, Wf at P+1 points
   int P = d->P, Q = d->Q, n = P + 1;
-  int TS = 2 * Q * n + Q + 3 * Q * n + n * n + n;
-  std::vector<double> tab(TS, 0.0), xq(Q), wq(Q), v(n), dv(n);
-  sdme::gauss_legendre(Q, xq.data(), wq.data());
-  for (int q = 0; q < Q; q++) {
-    c->basis.eval(xq[q], v.data(), dv.data());
-    for (int s = 0; s < n; s++) {
-      tab[q * n + s] = v[s];
-      tab[Q * n + q * n + s] = dv[s];
-      int o = 2 * Q * n + Q;
-      tab[o + q * n + s] = v[s] * v[s];
-      tab[o + Q * n + q * n + s] = dv[s] * dv[s];
-      tab[o + 2 * Q * n + q * n + s] = v[s] * dv[s];
-    }
-    tab[2 * Q * n + q] = wq[q];
-  }
-  std::vector<double> xf(n), wf(n);
-  sdme::gauss_legendre(n, xf.data(), wf.data());
-  int of = 2 * Q * n + Q + 3 * Q * n;
-  for (int i = 0; i < n; i++) {
-    c->basis.eval(xf[i], v.data(), nullptr);
-    for (int s = 0; s < n; s++) tab[of + i * n + s] = v[s];
-    tab[of + n * n + i] = wf[i];
+  std::vector<double> tab;
+  if (!build_tables(c->basis, P, Q, tab) ||
+      (d->mass_rule == 1 && !build_tables(c->basis, P, P + 1, c->tabm_host))) {
+    delete c;
+    return SDME_EEIG;
   }
   c->tab_host = tab;
   MeshK<double> &m = c->m64;
   m.nx = d->nx; m.ny = d->ny; m.nz = d->nz; m.E = (int)E;
-  m.Nx = (int)Nx; m.Ny = (int)Ny; m.Nz = (int)Nz; m.Nn = (int)Nn;
+  m.Nx = (int)Nx; m.Ny = (int)Ny; m.Nz = (int)Nz; m.Nn = (int)Nn; m.Q = Q;
   m.bc = d->dirichlet;
   for (int j = 0; j < 3; j++) m.ih[j] = 2.0 / d->h[j];
   m.detJ = d->h[0] * d->h[1] * d->h[2] / 8.0;
@@ -476,7 +523,7 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   m.flag = nullptr;
   MeshK<float> &f = c->m32;
   f.nx = m.nx; f.ny = m.ny; f.nz = m.nz; f.E = m.E;
-  f.Nx = m.Nx; f.Ny = m.Ny; f.Nz = m.Nz; f.Nn = m.Nn;
+  f.Nx = m.Nx; f.Ny = m.Ny; f.Nz = m.Nz; f.Nn = m.Nn; f.Q = m.Q;
   f.bc = m.bc;
   for (int j = 0; j < 3; j++) f.ih[j] = (float)m.ih[j];
   f.detJ = (float)m.detJ;
@@ -639,7 +686,8 @@ extern "C" int sdme_tangent_apply(sdme_ctx *c, const sdme_material *mat, int pre
                                   const void *u_lin, const void *state, double mass_shift,
                                   const void *v, void *y, int flags, void *stream) {
   if (!c || !mat || !mat->mu || !mat->lam || !v || !y || !valid_prec(prec) ||
-      (u_lin == nullptr) == (state == nullptr) || !std::isfinite(mass_shift))
+      (u_lin == nullptr) == (state == nullptr) || !std::isfinite(mass_shift) ||
+      (c->d.mass_rule && mass_shift != 0.0))
     return SDME_EINVAL;
   if (int rc_ = ensure_device(c)) return rc_;
   hipStream_t st = S(stream);
@@ -674,18 +722,20 @@ extern "C" int sdme_mass_apply(sdme_ctx *c, double rho, int prec, const void *v,
   Reduce none{c->partials, c->counter, c->results + 8};
   if (prec == SDME_FP64) {
     if (launch_fill<double>((double *)y, 0.0, N, st)) return SDME_EDEVICE;
-    return lerr(launch_mass<double>(c->P, c->m64, rho, (const double *)v, (double *)y, mask, none,
+    return lerr(launch_mass<double>(c->P, c->mm64, rho, (const double *)v, (double *)y, mask, none,
                                     0, nullptr, st));
   }
   if (launch_fill<float>((float *)y, 0.0f, N, st)) return SDME_EDEVICE;
-  return lerr(launch_mass<float>(c->P, c->m32, (float)rho, (const float *)v, (float *)y, mask,
+  return lerr(launch_mass<float>(c->P, c->mm32, (float)rho, (const float *)v, (float *)y, mask,
                                  none, 0, nullptr, st));
 }
 
 extern "C" int sdme_jacobi_diag(sdme_ctx *c, const sdme_material *mat, int prec,
                                 const void *state, double mass_shift, void *d, int flags,
                                 void *stream) {
-  if (!c || !mat || !mat->mu || !mat->lam || !state || !d || !valid_prec(prec)) return SDME_EINVAL;
+  if (!c || !mat || !mat->mu || !mat->lam || !state || !d || !valid_prec(prec) ||
+      (c->d.mass_rule && mass_shift != 0.0))
+    return SDME_EINVAL;
   if (int rc_ = ensure_device(c)) return rc_;
   hipStream_t st = S(stream);
   int64_t N = 3 * c->Nn;
@@ -751,7 +801,7 @@ extern "C" int sdme_quadrature_points(const sdme_ctx *c, int face, double *o) {
   if (face < 0) {
     const int Q = c->Q, Q3 = Q * Q * Q;
     std::vector<double> x(Q), w(Q);
-    sdme::gauss_legendre(Q, x.data(), w.data());
+    sdme::volume_rule(c->P, Q, x.data(), w.data());
     for (int64_t e = 0; e < c->E; e++) {
       const int ei[3] = {(int)(e % d.nx), (int)((e / d.nx) % d.ny), (int)(e / ((int64_t)d.nx * d.ny))};
       for (int q = 0; q < Q3; q++) {
@@ -873,7 +923,8 @@ extern "C" int sdme_jacobi_pcg(sdme_ctx *c, const sdme_material *mat, int prec, 
                                int maxit, double inner_rtol, sdme_stats *stats, void *ws,
                                size_t ws_bytes, void *stream) {
   if (!c || !mat || !mat->mu || !mat->lam || !b || !x || !valid_prec(prec) ||
-      (!mass_only && !u_lin) || !(rtol > 0) || maxit < 1 || !(inner_rtol > 0 && inner_rtol < 1))
+      (!mass_only && !u_lin) || !(rtol > 0) || maxit < 1 || !(inner_rtol > 0 && inner_rtol < 1) ||
+      (c->d.mass_rule && !mass_only && shift != 0.0))
     return SDME_EINVAL;
   if (int rc_ = ensure_device(c)) return rc_;
   Timer tm;
@@ -957,7 +1008,7 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
           launch_fill<double>(du, 0.0, N, st))
         return SDME_EDEVICE;
       Reduce none{c->partials, c->counter, c->results + 8};
-      if (launch_mass<double>(c->P, c->m64, mat->rho, acc, du, 1, none, 0, nullptr, st))
+      if (launch_mass<double>(c->P, c->mm64, mat->rho, acc, du, 1, none, 0, nullptr, st))
         return SDME_EDEVICE;
       if (launch_axpby(psi, -1.0, du, 1.0, N, st)) return SDME_EDEVICE;
     }
@@ -1012,6 +1063,7 @@ extern "C" int sdme_newmark_newton_step(sdme_ctx *c, const sdme_material *mat, i
                                         sdme_stats *stats, void *ws, size_t ws_bytes,
                                         void *stream) {
   if (!c || !mat || !mat->mu || !mat->lam || !u || !v || !a || !valid_prec(prec) || !(dt > 0) ||
+      c->d.mass_rule ||
       !(beta > 0) || !(gamma > 0) || !(newton_rtol > 0) || !(pcg_rtol > 0) || max_newton < 0 ||
       max_pcg < 1)
     return SDME_EINVAL;
@@ -1165,8 +1217,9 @@ extern "C" int sdme_energies(sdme_ctx *c, const sdme_material *mat, const double
   // v = (u_next - u_prev) / (2 dt); KE = 1/2 v^T M v (fused element-local dot)
   if (launch_axpbypcz(w.t1, 0.5 / dt, u_next, 0.0, -0.5 / dt, u_prev, N, st) ||
       launch_fill<double>(w.t2, 0.0, N, st) ||
-      launch_mass<double>(c->P, c->m64, mat->rho, w.t1, w.t2, 0, red_at(c, 12), 1, nullptr, st) ||
-      launch_fin2(red_at(c, 12), elem_blocks(c->P, 8, c->d.nx, c->d.ny, c->d.nz, false), st))
+      launch_mass<double>(c->P, c->mm64, mat->rho, w.t1, w.t2, 0, red_at(c, 12), 1, nullptr, st) ||
+      launch_fin2(red_at(c, 12),
+                  elem_blocks(c->P, c->mm64.Q, 8, c->d.nx, c->d.ny, c->d.nz, false), st))
     return SDME_EDEVICE;
   if (hipMemcpyAsync(c->h_res, c->results + 12, sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
@@ -1216,7 +1269,7 @@ extern "C" int sdme_lambda_max(sdme_ctx *c, const sdme_material *mat, const doub
     if (ct && launch_face(c->P, c->m64, 2, 4, nullptr, 1.0, ct->eps, 0, 0, x, y, red_at(c, 11), 0, st))
       return SDME_EDEVICE;
     if (launch_bc<double>(y, 0, c->m64, st) || launch_fill<double>(mx, 0.0, N, st) ||
-        launch_mass<double>(c->P, c->m64, mat->rho, x, mx, 1, none, 0, nullptr, st))
+        launch_mass<double>(c->P, c->mm64, mat->rho, x, mx, 1, none, 0, nullptr, st))
       return SDME_EDEVICE;
     double a[2], b[2];
     if ((rc = dot2<double>(c, x, y, N, a, st)) || (rc = dot2<double>(c, x, mx, N, b, st))) return rc;

@@ -149,6 +149,18 @@ static bool gll_points(int P, double *z) {
   return true;
 }
 
+// Gauss-Lobatto-Legendre rule of Q points (exact to degree 2Q - 3): the GLL
+// points of order Q - 1 with weights 2 / (Q (Q - 1) L_{Q-1}(x)^2).
+bool gll_rule(int Q, double *x, double *w) {
+  if (Q < 2 || !gll_points(Q - 1, x)) return false;
+  for (int i = 0; i < Q; i++) {
+    double p, dp;
+    legendre(Q - 1, x[i], &p, &dp);
+    w[i] = 2.0 / (Q * (Q - 1.0) * p * p);
+  }
+  return true;
+}
+
 static void nodal_eval(int P, const double *z, double x, double *v, double *d) {
   int n = P + 1;
   for (int a = 0; a < n; a++) {

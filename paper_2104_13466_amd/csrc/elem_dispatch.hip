@@ -80,12 +80,15 @@ int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double 
 #undef C
 }
 
-int elem_blocks(int P, int word, int nx, int ny, int nz, bool grad) {
+int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad) {
   int ne = 1;
-  switch (P * 10 + (word == 8 ? 1 : 0)) {
-#define NEC(p)                                                                               \
-  case p * 10 + 1: ne = grad ? Dims<p, p + 2, 8>::NE : Dims<p, p + 2, 8, false>::NE; break; \
-  case p * 10 + 0: ne = grad ? Dims<p, p + 2, 4>::NE : Dims<p, p + 2, 4, false>::NE; break;
+  const int g = Q == P + 1 ? 1 : 0;
+  switch (P * 100 + g * 10 + (word == 8 ? 1 : 0)) {
+#define NEC(p)                                                                                   \
+  case p * 100 + 1: ne = grad ? Dims<p, p + 2, 8>::NE : Dims<p, p + 2, 8, false>::NE; break;     \
+  case p * 100 + 0: ne = grad ? Dims<p, p + 2, 4>::NE : Dims<p, p + 2, 4, false>::NE; break;     \
+  case p * 100 + 11: ne = grad ? Dims<p, p + 1, 8>::NE : Dims<p, p + 1, 8, false>::NE; break;    \
+  case p * 100 + 10: ne = grad ? Dims<p, p + 1, 4>::NE : Dims<p, p + 1, 4, false>::NE; break;
     NEC(1) NEC(2) NEC(3) NEC(4) NEC(5) NEC(6) NEC(7) NEC(8)
 #undef NEC
     default: ne = 1;

@@ -1168,10 +1168,11 @@ __global__ __launch_bounds__((EK<P, Q, double>::NT)) void k_matgrad(
 }
 
 // ============================================================ launch wrappers
-template <int P, typename T>
-int launch_force_t(const MeshK<T> &m, const double *mu, const double *lam, const T *u, T *R,
+// Each wrapper dispatches on the volume rule of the mesh: Q = P + 2
+// Gauss-Legendre points or Q = P + 1 Gauss-Lobatto-Legendre points.
+template <int P, int Q, typename T>
+int launch_force_q(const MeshK<T> &m, const double *mu, const double *lam, const T *u, T *R,
                           T *state, int mask, hipStream_t st) {
-  constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   if (R && state)
@@ -1182,12 +1183,17 @@ int launch_force_t(const MeshK<T> &m, const double *mu, const double *lam, const
     hipLaunchKernelGGL((k_force<P, Q, T, true, false>), grid, block, 0, st, m, mu, lam, u, R, state, mask);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-
 template <int P, typename T>
-int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
+int launch_force_t(const MeshK<T> &m, const double *mu, const double *lam, const T *u, T *R,
+                          T *state, int mask, hipStream_t st) {
+  return m.Q == P + 1 ? launch_force_q<P, P + 1, T>(m, mu, lam, u, R, state, mask, st)
+                      : launch_force_q<P, P + 2, T>(m, mu, lam, u, R, state, mask, st);
+}
+
+template <int P, int Q, typename T>
+int launch_tangent_q(const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
                      const T *state, T msr, const T *v, T *y, int mask, const PUpd<T> *pu,
                      const int *skip, hipStream_t st) {
-  constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   const bool mass = msr != T(0);
@@ -1207,11 +1213,17 @@ int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, con
 #undef SDME_TAN
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-
 template <int P, typename T>
-int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
+int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
+                     const T *state, T msr, const T *v, T *y, int mask, const PUpd<T> *pu,
+                     const int *skip, hipStream_t st) {
+  return m.Q == P + 1 ? launch_tangent_q<P, P + 1, T>(m, mu, lam, ulin, state, msr, v, y, mask, pu, skip, st)
+                      : launch_tangent_q<P, P + 2, T>(m, mu, lam, ulin, state, msr, v, y, mask, pu, skip, st);
+}
+
+template <int P, int Q, typename T>
+int launch_mass_q(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
                   const int *skip, hipStream_t st) {
-  constexpr int Q = P + 2;
   using K = EK<P, Q, T, false>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   if (do_red)
@@ -1220,36 +1232,57 @@ int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce r
     hipLaunchKernelGGL((k_mass<P, Q, T, false>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-
 template <int P, typename T>
-int launch_diag_t(const MeshK<T> &m, const double *mu, const double *lam, const T *state,
+int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
+                  const int *skip, hipStream_t st) {
+  return m.Q == P + 1 ? launch_mass_q<P, P + 1, T>(m, rho, v, y, mask, red, do_red, skip, st)
+                      : launch_mass_q<P, P + 2, T>(m, rho, v, y, mask, red, do_red, skip, st);
+}
+
+template <int P, int Q, typename T>
+int launch_diag_q(const MeshK<T> &m, const double *mu, const double *lam, const T *state,
                          T msr, T *d, int mask, hipStream_t st) {
-  constexpr int Q = P + 2;
   using K = EK<P, Q, T>;
   static_assert(3 * K::n * K::n * Q <= K::SE, "diag LDS layout");
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_diag<P, Q, T>), grid, block, 0, st, m, mu, lam, state, msr, d, mask);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+template <int P, typename T>
+int launch_diag_t(const MeshK<T> &m, const double *mu, const double *lam, const T *state,
+                         T msr, T *d, int mask, hipStream_t st) {
+  return m.Q == P + 1 ? launch_diag_q<P, P + 1, T>(m, mu, lam, state, msr, d, mask, st)
+                      : launch_diag_q<P, P + 2, T>(m, mu, lam, state, msr, d, mask, st);
+}
 
-template <int P>
-int launch_energy_t(const MeshK<double> &m, const double *mu, const double *lam,
+template <int P, int Q>
+int launch_energy_q(const MeshK<double> &m, const double *mu, const double *lam,
                            const double *u, Reduce red, hipStream_t st) {
-  constexpr int Q = P + 2;
   using K = EK<P, Q, double>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_energy<P, Q>), grid, block, 0, st, m, mu, lam, u, red);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
-
 template <int P>
-int launch_matgrad_t(const MeshK<double> &m, const double *u, const double *w, double scale,
+int launch_energy_t(const MeshK<double> &m, const double *mu, const double *lam,
+                           const double *u, Reduce red, hipStream_t st) {
+  return m.Q == P + 1 ? launch_energy_q<P, P + 1>(m, mu, lam, u, red, st)
+                      : launch_energy_q<P, P + 2>(m, mu, lam, u, red, st);
+}
+
+template <int P, int Q>
+int launch_matgrad_q(const MeshK<double> &m, const double *u, const double *w, double scale,
                             double *gm, double *gl, hipStream_t st) {
-  constexpr int Q = P + 2;
   using K = EK<P, Q, double>;
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_matgrad<P, Q>), grid, block, 0, st, m, u, w, scale, gm, gl);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template <int P>
+int launch_matgrad_t(const MeshK<double> &m, const double *u, const double *w, double scale,
+                            double *gm, double *gl, hipStream_t st) {
+  return m.Q == P + 1 ? launch_matgrad_q<P, P + 1>(m, u, w, scale, gm, gl, st)
+                      : launch_matgrad_q<P, P + 2>(m, u, w, scale, gm, gl, st);
 }
 
 #ifdef SDME_P

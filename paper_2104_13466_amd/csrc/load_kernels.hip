@@ -3,7 +3,7 @@
 // tractions computed from a prescribed displacement field, Eq. of the
 // material virtual work in Section 3):
 //  - body load  f_a += sum_e sum_q w_q detJ N_a(X_q) b(X_q), b given at the
-//    volume Gauss points (Q = P+2 per direction);
+//    volume quadrature points of the mesh (Q per direction);
 //  - face load  f_a += int_face N_a t dA, t given at the face Gauss points
 //    (P+1 per direction, the rule of the contact face);
 //  - squared L2 error per component, sum_e sum_q w_q detJ (u_h(X_q) - g(X_q))^2.
@@ -26,10 +26,10 @@ __device__ __forceinline__ size_t grid_slot(const MeshK<double> &m, int P, int e
   return ((size_t)(ez * P + c) * m.Ny + (ey * P + b)) * m.Nx + (ex * P + a);
 }
 
-template <int P>
+template <int P, int Q>
 __global__ __launch_bounds__(NTL) void k_body_load(MeshK<double> m, const double *__restrict__ bq,
                                                    double *__restrict__ f) {
-  constexpr int n = P + 1, Q = P + 2, Q3 = Q * Q * Q;
+  constexpr int n = P + 1, Q3 = Q * Q * Q;
   using Dm = Dims<P, Q, 8>;
   __shared__ double sB[Q * n], sW[Q];
   __shared__ double s0[3 * Q3];         // weighted b [c][q3][q2][q1], then [c][q3][b][a]
@@ -92,9 +92,8 @@ __global__ __launch_bounds__(128) void k_face_load(MeshK<double> m, int face,
                                                    const double *__restrict__ t,
                                                    double *__restrict__ f) {
   constexpr int n = P + 1, nq = P + 1;
-  using Dm = Dims<P, P + 2, 8>;
   __shared__ double s_t[3 * nq * nq];
-  const double *Bf = m.tab + Dm::TBF, *Wf = m.tab + Dm::TWF;
+  const double *Bf = m.tab + face_table_offset(n, m.Q), *Wf = Bf + n * n;
   const int fe = blockIdx.x, nfe = gridDim.x;
   const FaceGeo g = face_geo(m, face, fe);
   for (int i = threadIdx.x; i < 3 * nq * nq; i += blockDim.x) {
@@ -121,11 +120,11 @@ __global__ __launch_bounds__(128) void k_face_load(MeshK<double> m, int face,
   }
 }
 
-template <int P>
+template <int P, int Q>
 __global__ __launch_bounds__(NTL) void k_l2_error(MeshK<double> m, const double *__restrict__ u,
                                                   const double *__restrict__ g,
                                                   double *__restrict__ partials) {
-  constexpr int n = P + 1, Q = P + 2, Q3 = Q * Q * Q;
+  constexpr int n = P + 1, Q3 = Q * Q * Q;
   using Dm = Dims<P, Q, 8>;
   __shared__ double sB[Q * n], sW[Q];
   __shared__ double s0[3 * n * Q * Q];  // coefficients [c][cc][b][a], then [c][cc][q2][q1]
@@ -197,9 +196,12 @@ __global__ __launch_bounds__(64) void k_sum3(const double *__restrict__ partials
   }
 
 int launch_body_load(int P, const MeshK<double> &m, const double *b, double *f, hipStream_t st) {
-#define BL(p)                                                                          \
-  case p:                                                                              \
-    hipLaunchKernelGGL(k_body_load<p>, dim3(m.E), dim3(NTL), 0, st, m, b, f); \
+#define BL(p)                                                                                  \
+  case p:                                                                                      \
+    if (m.Q == p + 1)                                                                          \
+      hipLaunchKernelGGL((k_body_load<p, p + 1>), dim3(m.E), dim3(NTL), 0, st, m, b, f);        \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_body_load<p, p + 2>), dim3(m.E), dim3(NTL), 0, st, m, b, f);        \
     break;
   SDME_PSWITCH(BL)
 #undef BL
@@ -221,9 +223,12 @@ int launch_face_load(int P, const MeshK<double> &m, int face, const double *t, d
 int launch_l2_error(int P, const MeshK<double> &m, const double *u, const double *g,
                     double *partials, int max_blocks, double *out, hipStream_t st) {
   const int nb = m.E < max_blocks ? m.E : max_blocks;
-#define LE(p)                                                                                \
-  case p:                                                                                    \
-    hipLaunchKernelGGL(k_l2_error<p>, dim3(nb), dim3(NTL), 0, st, m, u, g, partials); \
+#define LE(p)                                                                                  \
+  case p:                                                                                      \
+    if (m.Q == p + 1)                                                                          \
+      hipLaunchKernelGGL((k_l2_error<p, p + 1>), dim3(nb), dim3(NTL), 0, st, m, u, g, partials); \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_l2_error<p, p + 2>), dim3(nb), dim3(NTL), 0, st, m, u, g, partials); \
     break;
   SDME_PSWITCH(LE)
 #undef LE

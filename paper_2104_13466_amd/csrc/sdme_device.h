@@ -12,6 +12,10 @@
 
 namespace sdme {
 
+// Offset of the face tables (Bf [P+1][n], then Wf [P+1]) in the mesh tables
+// of Dims<P, Q>: they follow B, D, W, B*B, D*D, B*D.
+__host__ __device__ constexpr int face_table_offset(int n, int Q) { return 5 * Q * n + Q; }
+
 // GRAD = false sizes the LDS regions for value-only contractions (the mass
 // action: B tables only, one kind per stage).
 template <int P_, int Q_, int WORD, bool GRAD = true>
@@ -23,6 +27,7 @@ struct Dims {
   static constexpr int TB = 0, TD = Q * n, TW = 2 * Q * n, TB2 = 2 * Q * n + Q,
                        TD2 = TB2 + Q * n, TBD = TD2 + Q * n, TBF = TBD + Q * n,
                        TWF = TBF + n * n, TSIZE = TWF + n;
+  static_assert(TBF == face_table_offset(n, Q), "face table offset");
   // A block owns NE consecutive elements of one x-row of the mesh.  LDS:
   //  - per element, region A: the xi3-contracted fluxes g1..g3 of one
   //    component, [kind][c][q1][QP] with q2 fastest; region B: DBUF buffers
@@ -75,6 +80,7 @@ template <typename T>
 struct MeshK {
   int nx, ny, nz, E;
   int Nx, Ny, Nz, Nn;
+  int Q;         // volume points per direction: P + 2 (Gauss-Legendre) or P + 1 (GLL)
   uint32_t bc;   // Dirichlet bits (face*3 + comp)
   T ih[3];       // 2 / h_J  (reference-to-physical derivative scale)
   T detJ;        // h_x h_y h_z / 8

@@ -8,6 +8,12 @@
 namespace sdme {
 
 bool gauss_legendre(int Q, double *x, double *w);
+bool gll_rule(int Q, double *x, double *w);
+// The volume rule of a mesh: Gauss-Legendre for Q = P + 2, Gauss-Lobatto-
+// Legendre for Q = P + 1.
+inline bool volume_rule(int P, int Q, double *x, double *w) {
+  return Q == P + 1 ? gll_rule(Q, x, w) : gauss_legendre(Q, x, w);
+}
 
 // 1D basis held as a coefficient matrix T (slot x starting index) over its
 // starting basis (Jacobi modal, or Lagrange on GLL points for the nodal kind).

@@ -36,8 +36,9 @@ int launch_energy(int P, const MeshK<double> &m, const double *mu, const double 
                   const double *u, Reduce red, hipStream_t st);
 int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double *w, double scale,
                    double *gm, double *gl, hipStream_t st);
-// Blocks of an element kernel launch (grad = false: the value-only mass kernel).
-int elem_blocks(int P, int word, int nx, int ny, int nz, bool grad = true);
+// Blocks of an element kernel launch with Q points per direction (grad =
+// false: the value-only mass kernel).
+int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad = true);
 
 // ------------------------------------------------------------- face kernels
 // mode 0: traction f += scale * int N t dA on face `face`

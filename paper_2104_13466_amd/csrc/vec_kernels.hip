@@ -362,10 +362,9 @@ __global__ __launch_bounds__(128) void k_face(MeshK<double> m, int mode, int fac
                                               double z0, double origin_z, const double *u,
                                               double *f, Reduce red, int do_red) {
   constexpr int n = P + 1, nq = P + 1;
-  using Dm = Dims<P, P + 2, 8>;
   __shared__ double s_val[nq * nq];
   __shared__ double s_red[2];
-  const double *Bf = m.tab + Dm::TBF, *Wf = m.tab + Dm::TWF;
+  const double *Bf = m.tab + face_table_offset(n, m.Q), *Wf = Bf + n * n;
   int dir = face / 2, side = face % 2;
   int t1d = dir == 0 ? 1 : 0, t2d = dir == 2 ? 1 : 2;
   int ne[3] = {m.nx, m.ny, m.nz};

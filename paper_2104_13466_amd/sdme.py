@@ -34,7 +34,7 @@ class MeshDesc(ctypes.Structure):
                 ("P", ctypes.c_int), ("Q", ctypes.c_int), ("basis", ctypes.c_int),
                 ("k", ctypes.c_double), ("lambda_h", ctypes.c_double),
                 ("h", ctypes.c_double * 3), ("origin", ctypes.c_double * 3),
-                ("dirichlet", ctypes.c_uint32)]
+                ("dirichlet", ctypes.c_uint32), ("mass_rule", ctypes.c_int)]
 
 
 class Material(ctypes.Structure):
@@ -169,7 +169,7 @@ class Context:
     """Structured box mesh + basis (sdme_create / sdme_destroy)."""
 
     def __init__(self, n, L, P, basis=SDME_H, k=0.5, lambda_h=100.0, dirichlet=0, origin=(0, 0, 0),
-                 Q=None):
+                 Q=None, lumped_mass=False):
         self.L = _lib()
         self.P, self.Q = P, (P + 2 if Q is None else Q)
         d = MeshDesc()
@@ -180,6 +180,7 @@ class Context:
             d.h[i] = L[i] / n[i] if n[i] > 0 else 0.0
             d.origin[i] = origin[i]
         d.dirichlet = dirichlet
+        d.mass_rule = 1 if lumped_mass else 0
         self.desc = d
         self.n = tuple(n)
         self.h = [d.h[i] for i in range(3)]

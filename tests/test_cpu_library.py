@@ -78,4 +78,34 @@ def test_argument_validation():
     with pytest.raises(sdme.SdmeError):
         sdme.Context((0, 2, 2), (1, 1, 1), 3)
     with pytest.raises(sdme.SdmeError):
-        sdme.Context((2, 2, 2), (1, 1, 1), 3, Q=4)  # only Q = P+2 is compiled
+        sdme.Context((2, 2, 2), (1, 1, 1), 3, Q=6)  # only Q = P+2 and P+1 are compiled
+    with pytest.raises(sdme.SdmeError):
+        sdme.Context((2, 2, 2), (1, 1, 1), 3, Q=3)
+
+
+def test_context_accepts_gll_rule():
+    # Q = P+1 selects the Gauss-Lobatto-Legendre volume rule (host-only query)
+    c = sdme.Context((2, 1, 1), (1.0, 1.0, 1.0), 3, basis=ob.NODAL, Q=4)
+    X = c.quadrature_points()
+    # the GLL points include the element end points
+    assert abs(X[0, 0, 0]) < 1e-15 and abs(X[0, 0, 3] - 0.5) < 1e-15
+    c.close()
+
+
+def test_lumped_mass_rejects_mass_shifted_operators():
+    # the lumped mass is not fused into the mass-shifted tangent: such calls
+    # (and Newmark steps) are refused before any device access
+    import ctypes
+    c = sdme.Context((2, 1, 1), (1.0, 1.0, 1.0), 2, basis=ob.NODAL, lumped_mass=True)
+    m = sdme.Material()
+    m.mu, m.lam, m.rho = 8, 8, 1.0
+    p = ctypes.c_void_p(8)
+    rc = c.L.sdme_tangent_apply(c.handle, ctypes.byref(m), 0, None, p, 1.0, p, p, 0, None)
+    assert rc == -1
+    rc = c.L.sdme_jacobi_diag(c.handle, ctypes.byref(m), 0, p, 1.0, p, 0, None)
+    assert rc == -1
+    st = sdme.Stats()
+    rc = c.L.sdme_newmark_newton_step(c.handle, ctypes.byref(m), 0, p, p, p, None, 1e-3, 0.25,
+                                      0.5, 1e-8, 1e-8, 5, 100, ctypes.byref(st), None, 0, None)
+    assert rc == -1
+    c.close()

@@ -225,3 +225,48 @@ def test_wave_newmark_iteration_trend_matches_paper():
         its[kind] = pcg / newton
     assert its[ob.MODAL] >= 5.0 * its[ob.SDME_M]
     assert its[ob.MODAL] >= 5.0 * its[ob.SDME_H]
+
+
+# ------------------------------- Lagrange basis with a diagonal (lumped) mass
+def lumped_ctx(P):
+    import torch
+    ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=ob.NODAL, dirichlet=pf.DIRICHLET_X0,
+                  lumped_mass=True)
+    lam, mu = pf.lame()
+    mat = Context.material(torch.full((ctx.E,), mu, dtype=torch.float64, device="cuda"),
+                           torch.full((ctx.E,), lam, dtype=torch.float64, device="cuda"), pf.RHO)
+    return ctx, mat
+
+
+@pytest.mark.parametrize("P", [2, 5])
+def test_lumped_mass_matches_oracle_and_is_diagonal(P):
+    ctx, mat = lumped_ctx(P)
+    mm, _ = fb.static_mesh(P, ob.NODAL, Q=P + 1)
+    v = inputs.uniform(4, 3 * ctx.Nn, -1, 1)
+    import torch
+    y = torch.zeros(3 * ctx.Nn, dtype=torch.float64, device="cuda")
+    ctx.mass_apply(1.5, FP64, torch.as_tensor(v, device="cuda"), y)
+    ref = mm.mass_apply(1.5, v)
+    assert relerr(y.cpu().numpy(), ref) < TOL64
+    dg = mm.tangent_diag(np.zeros(mm.E), np.zeros(mm.E), np.zeros_like(v), 1.5)
+    assert relerr(ref, dg * v) < TOL64
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_wave_explicit_lagrange_diagonal_mass_matches_paper(P):
+    ctx, mat = lumped_ctx(P)
+    u, mass_its = pf.wave_explicit(ctx, mat, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, FP64)
+    eg, _ = wave_ctx(P, ob.NODAL)  # error by the Gauss rule of P+2 points
+    err = eg.l2_error(u, pf.exact_at_gauss_points(eg, "wave", 0.25))
+    ref = paper_wave_l2()[("explicit", "lagrange_diag", P)]
+    print("explicit lumped P=%d L2 %s paper %s mass its/step %.2f" % (
+        P, err, ref, mass_its / WAVE_STEPS_EXPLICIT))
+    check_paper(P, err, ref)
+    assert mass_its <= WAVE_STEPS_EXPLICIT  # a diagonal mass: one PCG iteration per solve
+
+
+def test_wave_explicit_lagrange_diagonal_mass_matches_oracle_p2():
+    ctx, mat = lumped_ctx(2)
+    u, _ = pf.wave_explicit(ctx, mat, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, FP64)
+    uo, _ = fb.wave_explicit(2, ob.NODAL, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, lumped=True)
+    assert relerr(u.cpu().numpy(), uo) < 1e-7

@@ -3,7 +3,9 @@ by element on the same seeded inputs: internal force, tangent action (stored
 state and recomputed, with mass shift, masked), mass, Jacobi diagonal, strain
 energy, material sensitivities, face traction and penalty contact.  Mesh rows
 span several element blocks with a ragged tail; every order P = 1..8 and every
-basis kind is covered; Dirichlet faces touch both ends of the rows.  Tolerances: 1e-12 (FP64), 1e-5 (FP32) relative in the max norm."""
+basis kind is covered, with the Gauss-Legendre rule (P+2 points) and, for four
+orders, the Gauss-Lobatto-Legendre rule (P+1 points); Dirichlet faces touch
+both ends of the rows.  Tolerances: 1e-12 (FP64), 1e-5 (FP32) relative in the max norm."""
 import numpy as np
 import pytest
 
@@ -28,20 +30,30 @@ CASES = [
     ((5, 2, 1), 6, ob.SDME_K),
     ((4, 2, 1), 7, ob.MODAL),
     ((3, 1, 1), 8, ob.SDME_H),
+    # Gauss-Lobatto-Legendre volume rule of P+1 points (collocated with the
+    # nodal basis: diagonal mass)
+    ((40, 2, 1), 1, ob.NODAL, "gll"),
+    ((13, 2, 1), 3, ob.NODAL, "gll"),
+    ((10, 1, 2), 4, ob.SDME_H, "gll"),
+    ((5, 2, 1), 7, ob.NODAL, "gll"),
 ]
-IDS = ["P%d-%s" % (c[1], ob.KIND_NAMES[c[2]]) for c in CASES]
+IDS = ["P%d-%s%s" % (c[1], ob.KIND_NAMES[c[2]], "-gll" if len(c) > 3 else "") for c in CASES]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=IDS)
 def pair(request):
-    n, P, kind = request.param
+    n, P, kind = request.param[:3]
+    Q = P + 1 if len(request.param) > 3 else None
     mu, lam = inputs.lognormal_lame(100 + P, n[0] * n[1] * n[2], 1.0e3, 0.3)
     bc = inputs.face_bits(0) | inputs.face_bits(1, comps=(2,)) | inputs.face_bits(3, comps=(0, 1))
-    return Pair(n, (1.0, 0.75, 1.25), P, kind=kind, dirichlet=bc, mu=mu, lam=lam, rho=1.7)
+    return Pair(n, (1.0, 0.75, 1.25), P, kind=kind, dirichlet=bc, mu=mu, lam=lam, rho=1.7, Q=Q)
 
 
 def _inputs(p, seed):
-    u = p.rand(seed, 0.004)
+    # the GLL points crowd at the element ends (spacing ~ h / P^2), where
+    # random nodal values of the nodal basis give large gradients: a smaller
+    # amplitude keeps det F > 0 there
+    u = p.rand(seed, 0.004 if p.ctx.Q == p.P + 2 else 0.0005)
     v = inputs.uniform(seed, p.N, -1, 1, stream=7)
     return u, v
 
@@ -177,3 +189,18 @@ def test_surface_terms(pair):
 def test_gather_and_dirichlet(pair):
     assert np.array_equal(pair.ctx.gather_indices(), pair.pb.mesh.gather_map())
     assert np.array_equal(pair.ctx.dirichlet_flags(), (pair.mask == 0).astype(np.uint8))
+
+
+def test_gll_nodal_mass_is_diagonal(pair):
+    # the nodal basis collocated with the GLL rule has a diagonal mass: the
+    # mass action equals the diagonal (from jacobi_diag with zero Lame
+    # parameters) times the vector
+    if pair.ctx.Q != pair.P + 1 or pair.basis.kind != ob.NODAL:
+        pytest.skip("nodal basis with the GLL rule only")
+    v = inputs.uniform(3, pair.N, -1, 1)
+    y = pair.zeros()
+    pair.ctx.mass_apply(2.0, FP64, pair.dev(v), y)
+    ref = pair.pb.mesh.mass_apply(2.0, v)
+    dg = pair.pb.mesh.tangent_diag(0 * pair.pb.mu, 0 * pair.pb.lam, 0 * v, 2.0)
+    assert relerr(pair.host(y), dg * v) < TOL64
+    assert relerr(ref, dg * v) < TOL64

@@ -182,3 +182,32 @@ def test_affine_coefficients(P, kind):
     # vertex coefficients are the vertex values
     assert abs(g1[0] - 1) < 1e-12 and abs(g1[P] - 1) < 1e-12
     assert abs(gx[0] + 1) < 1e-12 and abs(gx[P] - 1) < 1e-12
+
+
+def test_gll_rule_closed_forms_and_exactness():
+    # Q = 2: the trapezoidal rule; Q = 3: Simpson's rule; exact to degree 2Q - 3
+    x, w = ob.gll_rule(2)
+    assert np.allclose(x, [-1, 1], atol=1e-15) and np.allclose(w, [1, 1], atol=1e-15)
+    x, w = ob.gll_rule(3)
+    assert np.allclose(x, [-1, 0, 1], atol=1e-15)
+    assert np.allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    for Q in range(2, 11):
+        x, w = ob.gll_rule(Q)
+        for d in range(2 * Q - 2):
+            exact = 0.0 if d % 2 else 2.0 / (d + 1)
+            assert abs(w @ x ** d - exact) < 1e-13
+        # degree 2Q - 2 is not integrated exactly
+        d = 2 * Q - 2
+        assert abs(w @ x ** d - 2.0 / (d + 1)) > 1e-6
+
+
+@pytest.mark.parametrize("P", [1, 2, 4, 7])
+def test_nodal_basis_with_gll_rule_has_diagonal_mass(P):
+    # Lagrange basis on the GLL points, integrated with the same points: the
+    # 1D mass B^T W B is diagonal (collocation), and so is the element mass
+    # M1 x M1 x M1
+    b, x, w, B, D = ob.build(P, P + 1, ob.NODAL)
+    M = B.T @ np.diag(w) @ B
+    assert np.abs(M - np.diag(np.diag(M))).max() < 1e-14 * np.abs(M).max()
+    # and the mass weights are the GLL weights (vertex slots first/last)
+    assert np.allclose(np.sort(np.diag(M)), np.sort(w), atol=1e-14)

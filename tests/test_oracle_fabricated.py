@@ -159,3 +159,13 @@ def test_wave_newmark_reproduces_paper_l2_errors_p2():
     _, err, newton, its = fb.wave_newmark(2, ob.SDME_H, WAVE_DT_NEWMARK, WAVE_STEPS_NEWMARK)
     assert within_factor(err, paper_wave_l2()[("newmark", "sdme_h", 2)], 1.25), err
     assert newton >= WAVE_STEPS_NEWMARK
+
+
+def test_wave_explicit_lagrange_diagonal_mass_reproduces_paper_p2():
+    # Table Tab:Transient_NH_L2errorHexa_Lagrange at P = 2: the nodal basis
+    # with the mass integrated by the P+1 GLL points (diagonal), the internal
+    # force by the Gauss rule
+    _, err = fb.wave_explicit(2, ob.NODAL, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, lumped=True)
+    ref = paper_wave_l2()[("explicit", "lagrange_diag", 2)]
+    assert within_factor(err[0], ref[0], 1.25), err
+    assert within_factor(err[1:], ref[1:], 1.5), err
