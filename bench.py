@@ -562,9 +562,10 @@ def case_static(a):
 def case_wave(a):
     """Transient fabricated solution of Section 5.2 (u_x = sin(pi x / 2)
     sin(2 pi t) on the 2x2x2 unit cube to t = 0.25, x = 0 clamped):
-    central differences (800 steps) and Newmark (dt = 2e-3, 125 steps, Newton
-    and Jacobi-PCG to 1e-8), P = 2, 4, 6; L2 errors, iterations and times
-    beside the paper's tables (Tab:Transient_NH_L2errorHexa_ST, _SDME_M,
+    central differences (800 steps; also with the nodal basis and the lumped
+    GLL-rule mass) and Newmark (dt = 2e-3, 125 steps, Newton and Jacobi-PCG to
+    1e-8), P = 2, 4, 6; L2 errors, iterations and times beside the paper's
+    tables (Tab:Transient_NH_L2errorHexa_ST, _SDME_M, _Lagrange,
     Tab:TransientNmk_NH_L2errorHexa_SDME_H, Tab:TransientNmk_NH_NIT_Hexa,
     Tab:TransientNmk_NH_time_Hexa)."""
     import torch
@@ -578,8 +579,9 @@ def case_wave(a):
             ref[(v[0], v[1], int(v[2]))] = [float(x) for x in v[4:]]
     nit = _golden("wave_newmark_cgd_iterations.txt")
 
-    def mk(P, kind):
-        ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=kind, dirichlet=pf.DIRICHLET_X0)
+    def mk(P, kind, lumped=False):
+        ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=kind, dirichlet=pf.DIRICHLET_X0,
+                      lumped_mass=lumped)
         lam, mu = pf.lame()
         mat = Context.material(torch.full((ctx.E,), mu, dtype=torch.float64, device="cuda"),
                                torch.full((ctx.E,), lam, dtype=torch.float64, device="cuda"), pf.RHO)
@@ -587,13 +589,14 @@ def case_wave(a):
 
     rows = []
     for P in (2, 4, 6):
-        runs = [("explicit", 2, FP64), ("explicit", 2, FP32), ("newmark", 4, FP64),
-                ("newmark", 4, FP32), ("newmark", 2, FP64), ("newmark", 1, FP64)]
+        runs = [("explicit", 2, FP64), ("explicit", 2, FP32), ("explicit-lumped", 0, FP64),
+                ("newmark", 4, FP64), ("newmark", 4, FP32), ("newmark", 2, FP64),
+                ("newmark", 1, FP64)]
         if P <= 4:
             runs.append(("explicit", 1, FP64))
         for scheme, kind, prec in runs:
-            ctx, mat = mk(P, kind)
-            if scheme == "explicit":
+            ctx, mat = mk(P, kind, lumped=scheme == "explicit-lumped")
+            if scheme.startswith("explicit"):
                 (u, its), ms = timed(lambda: pf.wave_explicit(ctx, mat, 0.25 / 800, 800, prec))
                 row = {"steps": 800, "mass_pcg_per_step": round(its / 800, 1),
                        "ms_per_step": round(ms / 800, 3), "force_prec": "fp64" if prec == FP64 else "fp32"}
@@ -604,9 +607,11 @@ def case_wave(a):
                        "paper_cgd_per_solve": nit[P][col], "ms_per_step": round(ms / 125, 3),
                        "prec": "fp64" if prec == FP64 else "mixed"}
             err = ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "wave", 0.25))
+            key = ("explicit", "lagrange_diag", P) if scheme == "explicit-lumped" else (
+                scheme, KIND_NAMES[kind], P)
             row.update({"scheme": scheme, "P": P, "basis": KIND_NAMES[kind],
                         "l2_error": [float("%.4g" % e) for e in err],
-                        "paper_l2_error": ref.get((scheme, KIND_NAMES[kind], P))})
+                        "paper_l2_error": ref.get(key)})
             log("wave %s" % row)
             rows.append(row)
             ctx.close()
