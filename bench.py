@@ -618,6 +618,41 @@ def case_wave(a):
     return {"case": "wave", "rows": rows}
 
 
+def case_quartic(a):
+    """Newmark runs of the fabricated solution u_x = x^4 sin(2 pi t) of
+    Section 5.2 (2x2x2 unit cube, T = 0.025, SDME-H, Newton and PCG to
+    1e-10): spatial convergence at dt = 3.9e-4 for P = 2..6 and time
+    convergence at P = 5 for 8..128 steps (the paper shows both only in a
+    figure, stating exponential convergence in space and a quadratic rate in
+    time)."""
+    import torch
+
+    from paper_2104_13466_amd import fabricated as pf
+    from paper_2104_13466_amd.sdme import FP64, Context
+    T = 0.025
+
+    def run(P, nsteps):
+        ctx = Context((2, 2, 2), (1.0, 1.0, 1.0), P, basis=4, dirichlet=pf.DIRICHLET_X0)
+        lam, mu = pf.lame()
+        mat = Context.material(torch.full((ctx.E,), mu, dtype=torch.float64, device="cuda"),
+                               torch.full((ctx.E,), lam, dtype=torch.float64, device="cuda"), pf.RHO)
+        (u, newton, pcg), ms = timed(lambda: pf.wave_newmark(
+            ctx, mat, T / nsteps, nsteps, FP64, newton_rtol=1e-10, pcg_rtol=1e-10, name="quartic"))
+        err = ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "quartic", T))
+        ctx.close()
+        return {"P": P, "steps": nsteps, "dt": T / nsteps, "l2_error": [float("%.4g" % e) for e in err],
+                "newton": newton, "pcg_per_solve": round(pcg / max(newton, 1), 2),
+                "ms_per_step": round(ms / nsteps, 3)}
+
+    space = [run(P, 64) for P in (2, 3, 4, 5, 6)]
+    time_ = [run(5, n) for n in (8, 16, 32, 64, 128)]
+    for r in space + time_:
+        log("quartic %s" % r)
+    rates = [time_[i]["l2_error"][0] / time_[i + 1]["l2_error"][0] for i in range(len(time_) - 1)]
+    return {"case": "quartic", "space_dt_3.9e-4": space, "time_P5": time_,
+            "time_error_ratios_per_halving": [round(x, 3) for x in rates]}
+
+
 # explicit time steps of the conrod runs of Section 5, per order
 CONROD_DT = {2: 6.06e-6, 3: 6.06e-6, 4: 3.03e-6, 5: 1.51e-6, 6: 1.51e-6, 7: 1.51e-6, 8: 7.58e-7}
 
@@ -729,7 +764,7 @@ def main():
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params",
-                                      "static", "wave", "conrod"],
+                                      "static", "wave", "conrod", "quartic"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
     ap.add_argument("--conrod-steps", type=int, default=6)
@@ -745,7 +780,7 @@ def main():
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
               "adjoint": case_adjoint, "params": case_params, "static": case_static,
-              "wave": case_wave, "conrod": case_conrod}[a.case]
+              "wave": case_wave, "conrod": case_conrod, "quartic": case_quartic}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)

@@ -235,6 +235,13 @@ def wave_field(X, t):
     return out
 
 
+def quartic_field(X, t):
+    """u* = (x^4 sin(2 pi t), 0, 0) (Section 5.2, implicit time integration)."""
+    out = np.zeros_like(X)
+    out[0] = X[0] ** 4 * np.sin(2.0 * np.pi * t)
+    return out
+
+
 _D2 = ((-2, -1.0 / 12), (-1, 16.0 / 12), (0, -30.0 / 12), (1, 16.0 / 12), (2, -1.0 / 12))
 
 
@@ -254,19 +261,19 @@ def dynamic_body_force(ufun_t, X, t, lam, mu, rho, delta=1e-3):
             body_force(lambda Y: ufun_t(Y, t), X, lam, mu, delta))
 
 
-def wave_loads(mesh, Bf, t):
+def wave_loads(mesh, Bf, t, field=wave_field):
     lam, mu = lame(E_STATIC, NU_STATIC)
     Xv = volume_points(mesh)
-    bv = dynamic_body_force(wave_field, Xv.reshape(3, -1), t, lam, mu, RHO_WAVE)
+    bv = dynamic_body_force(field, Xv.reshape(3, -1), t, lam, mu, RHO_WAVE)
     f = body_load(mesh, bv.reshape(Xv.shape))
     for face in range(1, 6):
         Xf = face_points(mesh, face)
-        tf = traction(lambda Y: wave_field(Y, t), face, Xf.reshape(3, -1), lam, mu)
+        tf = traction(lambda Y: field(Y, t), face, Xf.reshape(3, -1), lam, mu)
         f += face_load(mesh, face, Bf, tf.reshape(Xf.shape))
     return f
 
 
-def _wave_problem(P, kind, Q=None, lumped=False):
+def _wave_problem(P, kind, Q=None, lumped=False, field=wave_field):
     """Mesh, face table, problem and projected initial velocity of the wave
     example; lumped: the mass with the Gauss-Lobatto-Legendre rule of P+1
     points (diagonal for the nodal basis), the rest with the mesh's rule."""
@@ -279,7 +286,7 @@ def _wave_problem(P, kind, Q=None, lumped=False):
         pbm = osv.Problem(mm, pb.mu, pb.lam, RHO_WAVE, mask)
         pb.M, pb.mass_diag, pb.mass_solve = pbm.M, pbm.mass_diag, pbm.mass_solve
     Xv = volume_points(mesh)
-    vq = time_derivative(wave_field, Xv, 0.0, 1)
+    vq = time_derivative(field, Xv, 0.0, 1)
     # the initial velocity: L2 projection of du*/dt(0) (rho M v0 = rho int N v*)
     v0, _ = pb.mass_solve(RHO_WAVE * body_load(mesh, vq), 1e-13)
     return mesh, Bf, pb, v0
@@ -302,18 +309,18 @@ def wave_explicit(P, kind, dt, nsteps, mass_rtol=1e-12, Q=None, lumped=False):
     return u_cur, err
 
 
-def wave_newmark(P, kind, dt, nsteps, newton_rtol=1e-8, pcg_rtol=1e-8):
+def wave_newmark(P, kind, dt, nsteps, newton_rtol=1e-8, pcg_rtol=1e-8, field=wave_field):
     """Newmark (beta = 1/4, gamma = 1/2) with Newton from u = 0, the projected
     initial velocity and a_0 = M^-1 (f_0 - R(0)); returns (u, L2 errors,
     Newton iterations, PCG iterations per step)."""
-    mesh, Bf, pb, v = _wave_problem(P, kind)
+    mesh, Bf, pb, v = _wave_problem(P, kind, field=field)
     u = np.zeros(3 * mesh.Nn)
-    a, _ = pb.mass_solve(wave_loads(mesh, Bf, 0.0) - pb.R(u), 1e-13)
+    a, _ = pb.mass_solve(wave_loads(mesh, Bf, 0.0, field) - pb.R(u), 1e-13)
     newton, pcg_its = 0, []
     for n in range(nsteps):
-        u, v, a, nk, its = osv.newmark_step(pb, u, v, a, wave_loads(mesh, Bf, (n + 1) * dt), dt,
-                                            newton_rtol, pcg_rtol)
+        f = wave_loads(mesh, Bf, (n + 1) * dt, field)
+        u, v, a, nk, its = osv.newmark_step(pb, u, v, a, f, dt, newton_rtol, pcg_rtol)
         newton += nk
         pcg_its += its
-    err = l2_error(mesh, u, wave_field(volume_points(mesh), nsteps * dt))
+    err = l2_error(mesh, u, field(volume_points(mesh), nsteps * dt))
     return u, err, newton, pcg_its

@@ -40,8 +40,10 @@ def lame():
 #   static (Section 5.1):      w = 1.9 sin x - x
 #   wave (Section 5.2, Eq. eq:large_field): w = sin(pi x / 2) sin(2 pi t),
 #       t in [0, 0.25], rho = 1, explicit and Newmark integration
+#   quartic (Section 5.2, implicit time integration): w = x^4 sin(2 pi t),
+#       t in [0, 0.025], Newmark integration
 RHO = 1.0
-FIELDS = ("static", "wave")
+FIELDS = ("static", "wave", "quartic")
 
 
 def _w(name, x, t):
@@ -53,6 +55,11 @@ def _w(name, x, t):
         k, om = 0.5 * np.pi, 2.0 * np.pi
         sx, cx, st, ct = np.sin(k * x), np.cos(k * x), np.sin(om * t), np.cos(om * t)
         return sx * st, k * cx * st, -k * k * sx * st, om * sx * ct, -om * om * sx * st
+    if name == "quartic":
+        om = 2.0 * np.pi
+        st, ct = np.sin(om * t), np.cos(om * t)
+        return (x ** 4 * st, 4.0 * x ** 3 * st, 12.0 * x ** 2 * st, om * x ** 4 * ct,
+                -om * om * x ** 4 * st)
     raise ValueError(name)
 
 
@@ -147,20 +154,20 @@ def _projection(ctx, mat, name, t, prec):
     return x
 
 
-def wave_explicit(ctx, mat, dt, nsteps, prec_force, mass_rtol=1e-12):
+def wave_explicit(ctx, mat, dt, nsteps, prec_force, mass_rtol=1e-12, name="wave"):
     """Central differences from u = 0 and the projected initial velocity of
-    the wave field, external load of the field at every step; returns
-    (u at t = nsteps dt, total mass-PCG iterations)."""
+    the field, external load of the field at every step; returns (u at
+    t = nsteps dt, total mass-PCG iterations)."""
     import torch
     from .sdme import FP64
     N = 3 * ctx.Nn
     us = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(3)]
     f = torch.zeros(N, dtype=torch.float64, device="cuda")
-    v0 = _projection(ctx, mat, "wave", 0.0, FP64)
+    v0 = _projection(ctx, mat, name, 0.0, FP64)
     mass_its = 0
     for n in range(nsteps):
         f.zero_()
-        loads(ctx, "wave", f, n * dt)
+        loads(ctx, name, f, n * dt)
         prev, cur, nxt = us[(n + 2) % 3], us[n % 3], us[(n + 1) % 3]
         st = ctx.explicit_step(mat, prec_force, None if n == 0 else prev, cur, nxt, dt,
                                v0=v0 if n == 0 else None, f_ext=f, mass_rtol=mass_rtol)
@@ -168,7 +175,7 @@ def wave_explicit(ctx, mat, dt, nsteps, prec_force, mass_rtol=1e-12):
     return us[nsteps % 3], mass_its
 
 
-def wave_newmark(ctx, mat, dt, nsteps, prec, newton_rtol=1e-8, pcg_rtol=1e-8):
+def wave_newmark(ctx, mat, dt, nsteps, prec, newton_rtol=1e-8, pcg_rtol=1e-8, name="wave"):
     """Newmark (beta = 1/4, gamma = 1/2) with Newton from u = 0, the projected
     initial velocity and a_0 = M^-1 (f_0 - R(0)); returns (u at t = nsteps dt,
     Newton iterations, PCG iterations)."""
@@ -176,9 +183,9 @@ def wave_newmark(ctx, mat, dt, nsteps, prec, newton_rtol=1e-8, pcg_rtol=1e-8):
     from .sdme import FP64, MASK_BC
     N = 3 * ctx.Nn
     u = torch.zeros(N, dtype=torch.float64, device="cuda")
-    v = _projection(ctx, mat, "wave", 0.0, FP64)
+    v = _projection(ctx, mat, name, 0.0, FP64)
     f = torch.zeros_like(u)
-    loads(ctx, "wave", f, 0.0)
+    loads(ctx, name, f, 0.0)
     R = torch.zeros_like(u)
     ctx.internal_force(mat, FP64, u, R, flags=MASK_BC)
     ctx.axpby(1.0, f, -1.0, R)
@@ -187,7 +194,7 @@ def wave_newmark(ctx, mat, dt, nsteps, prec, newton_rtol=1e-8, pcg_rtol=1e-8):
     newton = pcg = 0
     for n in range(nsteps):
         f.zero_()
-        loads(ctx, "wave", f, (n + 1) * dt)
+        loads(ctx, name, f, (n + 1) * dt)
         st = ctx.newmark_newton_step(mat, prec, u, v, a, f, dt, newton_rtol=newton_rtol,
                                      pcg_rtol=pcg_rtol)
         newton += st["newton"]

@@ -270,3 +270,42 @@ def test_wave_explicit_lagrange_diagonal_mass_matches_oracle_p2():
     u, _ = pf.wave_explicit(ctx, mat, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, FP64)
     uo, _ = fb.wave_explicit(2, ob.NODAL, WAVE_DT_EXPLICIT, WAVE_STEPS_EXPLICIT, lumped=True)
     assert relerr(u.cpu().numpy(), uo) < 1e-7
+
+
+# ------------------- quartic field x^4 sin(2 pi t), Newmark (Section 5.2)
+QUARTIC_T = 0.025
+
+
+def test_quartic_newmark_time_convergence_is_quadratic():
+    # the paper: time convergence at P = 5 is quadratic for the Newmark
+    # method; x^4 lies in the P = 5 space, so the error is the time error
+    errs = []
+    for nsteps in (8, 16, 32):
+        ctx, mat = wave_ctx(5, ob.SDME_H)
+        u, _, _ = pf.wave_newmark(ctx, mat, QUARTIC_T / nsteps, nsteps, FP64, newton_rtol=1e-10,
+                                  pcg_rtol=1e-10, name="quartic")
+        errs.append(ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "quartic", QUARTIC_T))[0])
+    print("quartic P=5 errors", errs)
+    for a, b in zip(errs, errs[1:]):
+        assert 3.8 < a / b < 4.2
+
+
+def test_quartic_newmark_spatial_convergence_to_the_time_floor():
+    # dt = 3.9e-4 (the paper's), P = 2, 3, 4: the error falls by more than
+    # 1e4 from P = 2 to P = 4, where the spatial error is below the time error
+    errs = []
+    for P in (2, 3, 4, 5):
+        ctx, mat = wave_ctx(P, ob.SDME_H)
+        u, _, _ = pf.wave_newmark(ctx, mat, QUARTIC_T / 64, 64, FP64, name="quartic")
+        errs.append(ctx.l2_error(u, pf.exact_at_gauss_points(ctx, "quartic", QUARTIC_T))[0])
+    print("quartic dt=3.9e-4 errors P=2..5", errs)
+    assert errs[0] / errs[1] > 5 and errs[1] / errs[2] > 100
+    assert abs(errs[3] - errs[2]) < 0.05 * errs[2]  # the time floor
+
+
+def test_quartic_newmark_matches_oracle_p2():
+    ctx, mat = wave_ctx(2, ob.SDME_H)
+    u, newton, _ = pf.wave_newmark(ctx, mat, QUARTIC_T / 16, 16, FP64, name="quartic")
+    uo, _, newton_o, _ = fb.wave_newmark(2, ob.SDME_H, QUARTIC_T / 16, 16, field=fb.quartic_field)
+    assert relerr(u.cpu().numpy(), uo) < 1e-7
+    assert abs(newton - newton_o) <= max(1, 0.02 * newton_o)
