@@ -211,3 +211,26 @@ def test_nodal_basis_with_gll_rule_has_diagonal_mass(P):
     assert np.abs(M - np.diag(np.diag(M))).max() < 1e-14 * np.abs(M).max()
     # and the mass weights are the GLL weights (vertex slots first/last)
     assert np.allclose(np.sort(np.diag(M)), np.sort(w), atol=1e-14)
+
+
+def test_condition_numbers_follow_the_paper_figure():
+    # Fig. ConditionNumbers1D and its discussion (Section 2): the SDME-M mass
+    # (k = 1/2) is better conditioned than the ST mass and grows slowly with
+    # P; with k = 1 the SDME-M internal stiffness block has condition number 1;
+    # the SDME-H (lambda = 1, k = 1) equivalent stiffness K + M is almost
+    # constant in P while the ST one grows
+    c_st, c_m, c_h, c_hst = [], [], [], []
+    for P in range(2, 11):
+        st = ob.Basis1D(P, ob.MODAL)
+        sm = ob.Basis1D(P, ob.SDME_M, k=0.5)
+        sm1 = ob.Basis1D(P, ob.SDME_M, k=1.0)
+        sh = ob.Basis1D(P, ob.SDME_H, k=1.0, lam=1.0)
+        c_st.append(np.linalg.cond(st.M1))
+        c_m.append(np.linalg.cond(sm.M1))
+        assert abs(np.linalg.cond(sm1.K1[1:P, 1:P]) - 1.0) < 1e-10
+        c_h.append(np.linalg.cond(sh.K1 + sh.M1))
+        c_hst.append(np.linalg.cond(st.K1 + st.M1))
+    assert all(a < b / 10 for a, b in zip(c_m, c_st))
+    assert c_m[-1] / c_m[0] < c_st[-1] / c_st[0]
+    assert max(c_h) / min(c_h) < 1.05
+    assert c_hst[-1] / c_hst[0] > 1.5
