@@ -191,12 +191,12 @@ def test_gather_and_dirichlet(pair):
     assert np.array_equal(pair.ctx.dirichlet_flags(), (pair.mask == 0).astype(np.uint8))
 
 
-def test_gll_nodal_mass_is_diagonal(pair):
+@pytest.mark.parametrize("P", [1, 3, 7])
+def test_gll_nodal_mass_is_diagonal(P):
     # the nodal basis collocated with the GLL rule has a diagonal mass: the
-    # mass action equals the diagonal (from jacobi_diag with zero Lame
-    # parameters) times the vector
-    if pair.ctx.Q != pair.P + 1 or pair.basis.kind != ob.NODAL:
-        pytest.skip("nodal basis with the GLL rule only")
+    # mass action equals the diagonal (from the oracle's diagonal with zero
+    # Lame parameters) times the vector
+    pair = Pair((4, 2, 1), (1.0, 0.75, 1.25), P, kind=ob.NODAL, Q=P + 1)
     v = inputs.uniform(3, pair.N, -1, 1)
     y = pair.zeros()
     pair.ctx.mass_apply(2.0, FP64, pair.dev(v), y)
