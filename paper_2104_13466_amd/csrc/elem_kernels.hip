@@ -45,6 +45,14 @@ struct EK {
   // the element-private LDS exchanges of the contraction stages then need
   // only a wave-level synchronisation
   static constexpr bool WAVE_ELEM = 64 % QQ == 0;
+  // The xi1 contraction of the gradient kernels on the matrix cores: when one
+  // element fills one wave (Q^2 = 64) and the stacked [B; D] table has
+  // exactly 16 rows (2Q = 16, i.e. P = 6), in FP32 (v_mfma_f32_16x16x4f32).
+#ifndef SDME_MFMA_XI1
+#define SDME_MFMA_XI1 1
+#endif
+  static constexpr bool MFMA_XI1 =
+      SDME_MFMA_XI1 && std::is_same<T, float>::value && QQ == 64 && 2 * Dm::Q == 16 && n <= 8;
 };
 
 // Thread/element coordinates inside a block.  Block b owns the run of NE
@@ -325,6 +333,52 @@ __device__ __forceinline__ void stage1(const T *sB, const T *sD, const T *su, T 
   }
 }
 
+// xi1 contraction of one component on the matrix cores (EK::MFMA_XI1): the
+// 16 x 64 block out[(kind, q1)][(c, b)] = sum_a T_kind[q1][a] u[c][b][a]
+// (T_0 = B, T_1 = D; a padded from n to 8, the n^2 columns (c, b) padded to
+// 64) as four 16 x 16 tiles, each two 16x16x4 FP32 MFMA steps.  Operand
+// layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16], r = 0..3.  The
+// lane's two table entries (A rows = (kind, q1), columns a = l/16 and
+// l/16 + 4) are loaded once per kernel.
+struct MfmaTab {
+  float a0, a1;
+};
+template <class K>
+__device__ __forceinline__ MfmaTab mfma_xi1_table(const float *sB, const float *sD) {
+  constexpr int NP = K::Dm::NP;
+  static_assert(NP >= 8, "padded table rows hold 8 entries");
+  const int l = threadIdx.x & 63, m = l & 15, k = l >> 4;
+  const float *row = m < 8 ? sB + m * NP : sD + (m - 8) * NP;
+  return MfmaTab{row[k], row[k + 4]};  // entries past n are the rows' zero padding
+}
+template <class K>
+__device__ __forceinline__ void stage1_mfma(const MfmaTab &t, const float *su, float *st) {
+  constexpr int n = K::n, Q = K::Dm::Q, TX = K::TX, NP = K::Dm::NP;
+  static_assert(2 * Q == 16 && n <= 8 && n * n <= 64, "MFMA xi1 shape");
+  using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+  const int l = threadIdx.x & 63, col = l & 15, kr = l >> 4;
+#pragma unroll
+  for (int tt = 0; tt < 4; tt++) {
+    const int nn = col + 16 * tt;
+    const bool valid = nn < n * n;
+    const int c = valid ? nn / n : 0, b = valid ? nn % n : 0;
+    const float *urow = su + (c * n + b) * TX;
+    const float x0 = valid ? urow[kr] : 0.f;
+    const float x1 = (valid && kr + 4 < n) ? urow[kr + 4] : 0.f;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a0, x0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a1, x1, acc, 0, 0, 0);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int m = 4 * kr + r, kind = m >> 3, q1 = m & 7;
+        st[((kind * n + c) * Q + q1) * NP + b] = acc[r];
+      }
+    }
+  }
+}
+
 // xi2 contraction into registers at column (q1, q2) = (i1, i2): X[0][c]
 // (B in xi1, B in xi2), X[1][c] (B, D), X[2][c] (D, B).
 template <class K, typename T, bool GRAD>
@@ -381,7 +435,16 @@ __device__ __forceinline__ void forward_lds(const T *sB, const T *sD, const T *t
   constexpr int n = K::n, SB1 = K::Dm::SB1, CS = n * n * K::TX, NB = K::Dm::DBUF;
   const T *su = tile + s.le * K::Dm::P;
   const T *sD2 = sD + K::DS;
-  if constexpr (NB == 3) {
+  if constexpr (NB == 3 && GRAD && K::MFMA_XI1) {
+    const MfmaTab mt = mfma_xi1_table<K>(sB, sD);
+    stage1_mfma<K>(mt, su, st);
+    stage1_mfma<K>(mt, su + CS, st + SB1);
+    stage1_mfma<K>(mt, su + 2 * CS, st + 2 * SB1);
+    __syncthreads();
+    stage2<K, T, GRAD>(sB, sD2, st, s, X[0]);
+    stage2<K, T, GRAD>(sB, sD2, st + SB1, s, X[1]);
+    stage2<K, T, GRAD>(sB, sD2, st + 2 * SB1, s, X[2]);
+  } else if constexpr (NB == 3) {
     stage1<K, T, GRAD>(sB, sD, su, st, s);
     stage1<K, T, GRAD>(sB, sD, su + CS, st + SB1, s);
     stage1<K, T, GRAD>(sB, sD, su + 2 * CS, st + 2 * SB1, s);
