@@ -253,9 +253,10 @@ int sdme_face_load(sdme_ctx *ctx, int face, const double *t, double *f, void *st
 /* sdme_l2_error -- host_out[c] = ( sum_e sum_q w_q detJ (u_h,c(X_q) -
  * g_c(X_q))^2 )^(1/2) for c = 0, 1, 2: the L2 norm over the box of the
  * difference between the field with coefficients u (dev double [3][Nn]) and
- * the values g (dev double [3][E][Q^3] at the volume Gauss points), by the
- * volume rule of the mesh (Q points per direction).  Deterministic (block partials summed in block
- * order).  Synchronises.  Errors: SDME_EINVAL, SDME_EDEVICE. */
+ * the values g (dev double [3][E][Q^3] at the volume quadrature points), by
+ * the volume rule of the mesh (Q points per direction).  Deterministic (block
+ * partials summed in block order).  Synchronises.  Errors: SDME_EINVAL,
+ * SDME_EDEVICE. */
 int sdme_l2_error(sdme_ctx *ctx, const double *u, const double *g, double *host_out,
                   void *stream);
 

@@ -483,7 +483,8 @@ bool build_tables(const Basis &basis, int P, int Q, std::vector<double> &tab) {
 extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   if (!d || !out) return SDME_EINVAL;
   *out = nullptr;
-  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->P < 1 || d->P > 8 || (d->Q != d->P + 2 && d->Q != d->P + 1) || d->mass_rule < 0 || d->mass_rule > 1 ||
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->P < 1 || d->P > 8 ||
+      (d->Q != d->P + 2 && d->Q != d->P + 1) || d->mass_rule < 0 || d->mass_rule > 1 ||
       d->basis < 0 || d->basis > 4 || !(d->k >= 0 && d->k <= 1) || !(d->lambda_h >= 0) ||
       !(d->h[0] > 0 && d->h[1] > 0 && d->h[2] > 0) || (d->dirichlet >> 18) != 0)
     return SDME_EINVAL;
@@ -803,7 +804,8 @@ extern "C" int sdme_quadrature_points(const sdme_ctx *c, int face, double *o) {
     std::vector<double> x(Q), w(Q);
     sdme::volume_rule(c->P, Q, x.data(), w.data());
     for (int64_t e = 0; e < c->E; e++) {
-      const int ei[3] = {(int)(e % d.nx), (int)((e / d.nx) % d.ny), (int)(e / ((int64_t)d.nx * d.ny))};
+      const int ei[3] = {(int)(e % d.nx), (int)((e / d.nx) % d.ny),
+                         (int)(e / ((int64_t)d.nx * d.ny))};
       for (int q = 0; q < Q3; q++) {
         const int qi[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
         for (int k = 0; k < 3; k++)
