@@ -16,6 +16,10 @@
 
 using namespace sdme;
 
+#ifndef SDME_FUSED_PAP
+#define SDME_FUSED_PAP 1
+#endif
+
 struct sdme_ctx {
   sdme_mesh_desc d;
   int P, Q, n;
@@ -192,6 +196,10 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
     return SDME_EDEVICE;
   Reduce none{c->partials, c->counter, c->results + 8};
   const bool fused = p2 != nullptr && op.kind == 0;
+  // p^T A p formed by the FP64 fused operator (element energies)
+  const bool fused_pap = fused && SDME_FUSED_PAP && sizeof(T) == 8;
+  const int op_blocks =
+      elem_blocks(c->P, mk<T>(c).Q, (int)sizeof(T), c->d.nx, c->d.ny, c->d.nz, true);
   T *pb[2] = {p, p2};
   int par = 0;  // pb[par] holds the current search direction
   for (;;) {
@@ -223,7 +231,7 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
       T *pc = pb[par];
       if (fused) {
         // p_new = z + beta p_old formed in the operator's gather
-        PUpd<T> pu{r, d, pb[par ^ 1], &s->beta};
+        PUpd<T> pu{r, d, pb[par ^ 1], &s->beta, fused_pap ? c->partials : nullptr};
         if (apply_op<T>(c, mat, op, pc, Ap, none, 0, &s->done, st, &pu)) return SDME_EDEVICE;
         par ^= 1;
         pc = pb[par];
@@ -231,9 +239,13 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
         return SDME_EDEVICE;
       }
       if (c->prof && hipEventRecord(c->ev[2 * j + 1], st) != hipSuccess) return SDME_EDEVICE;
-      // p^T A p by a separate streaming dot (measured faster than partial sums
-      // fused into the operator kernel)
-      if (launch_pcg_pap<T>(pc, Ap, s, N, red_at(c, 6), st)) return SDME_EDEVICE;
+      // p^T A p: block partials of the element energies written by the FP64
+      // fused operator, else a separate streaming dot over p and A p
+      if (fused_pap) {
+        if (launch_pcg_pap_fin(s, red_at(c, 6), op_blocks, st)) return SDME_EDEVICE;
+      } else if (launch_pcg_pap<T>(pc, Ap, s, N, red_at(c, 6), st)) {
+        return SDME_EDEVICE;
+      }
       if (launch_pcg_update<T>(x, r, pc, Ap, d, s, N, red_at(c, 4), st)) return SDME_EDEVICE;
       if (!fused && launch_pcg_pupdate<T>(pc, r, d, s, N, st)) return SDME_EDEVICE;
     }

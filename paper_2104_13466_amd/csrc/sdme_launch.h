@@ -21,6 +21,9 @@ struct PUpd {
   const T *dinv;
   T *pnew;
   const double *beta;
+  // block partials [2 b] of p^T A p (the element-energy form, see the
+  // tangent kernel), summed by launch_pcg_pap_fin; nullptr: not formed
+  double *pap;
 };
 template <typename T>
 int launch_tangent(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
