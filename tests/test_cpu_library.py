@@ -109,3 +109,27 @@ def test_lumped_mass_rejects_mass_shifted_operators():
                                       0.5, 1e-8, 1e-8, 5, 100, ctypes.byref(st), None, 0, None)
     assert rc == -1
     c.close()
+
+
+def test_size_limits_and_load_argument_checks():
+    # 3 Nn must stay below 2^31 (int32 indices in the kernels): a 600^3 mesh
+    # at P = 2 (3 x 1201^3 DOF) is refused, 400^3 at P = 2 (3 x 801^3) is not
+    with pytest.raises(sdme.SdmeError) as e:
+        sdme.Context((600, 600, 600), (1.0, 1.0, 1.0), 2)
+    assert e.value.code == -1
+    c = sdme.Context((400, 400, 400), (1.0, 1.0, 1.0), 2)
+    assert c.Nn == 801 ** 3
+    c.close()
+    # loads at quadrature points: face index and pointers checked before any
+    # device access
+    import ctypes
+    c = sdme.Context((2, 1, 1), (1.0, 1.0, 1.0), 2)
+    p = ctypes.c_void_p(8)
+    assert c.L.sdme_face_load(c.handle, 6, p, p, None) == -1
+    assert c.L.sdme_face_load(c.handle, -1, p, p, None) == -1
+    assert c.L.sdme_body_load(c.handle, None, p, None) == -1
+    assert c.L.sdme_l2_error(c.handle, p, None, None, None) == -1
+    out = np.zeros(3 * c.E * c.Q ** 3)
+    assert c.L.sdme_quadrature_points(c.handle, 7, out.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double))) == -1
+    c.close()
