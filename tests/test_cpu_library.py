@@ -133,3 +133,15 @@ def test_size_limits_and_load_argument_checks():
     assert c.L.sdme_quadrature_points(c.handle, 7, out.ctypes.data_as(
         ctypes.POINTER(ctypes.c_double))) == -1
     c.close()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark is single-GPU: --gpus N > 1 exits with a message before
+    # touching a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
