@@ -233,3 +233,51 @@ def test_adjoint_gradient_matches_oracle_and_fd():
                              lam_t.detach() if arr is mu_t else a, keep=False)[0]
                 fd = (Jp - Jm) / (2 * h)
                 assert abs(fd - g[e].item()) < 1e-5 * abs(g[e].item()) + 1e-8 * g.abs().max().item()
+
+
+@pytest.mark.parametrize("P,kind,Q", [(2, ob.SDME_H, None), (4, ob.NODAL, 5), (3, ob.SDME_M, 4)],
+                         ids=["P2-gl", "P4-nodal-gll", "P3-sdme-m-gll"])
+def test_rigid_rotation_is_stress_free(P, kind, Q):
+    # u = (R - I) X with a finite rotation R: F = R at every point, S = 0, so
+    # the internal force vanishes to rounding (for either volume rule)
+    p = Pair((3, 2, 2), (1.0, 0.8, 0.6), P, kind=kind, Q=Q)
+    c, s = np.cos(0.7), np.sin(0.7)
+    Rz = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+    Rx = np.array([[1.0, 0, 0], [0, np.cos(0.4), -np.sin(0.4)], [0, np.sin(0.4), np.cos(0.4)]])
+    G = Rz @ Rx - np.eye(3)
+    u = p.ctx.affine_field([0.1, -0.2, 0.3], G)
+    R = p.zeros()
+    p.ctx.internal_force(p.mat, FP64, p.dev(u), R)
+    # scale: a unit strain gives element forces of order mu h^2
+    scale = p.pb.mu.max() * 0.8 * 0.6 / 4
+    assert np.abs(p.host(R)).max() < 1e-11 * scale
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_newton_static_compression_gll_rule(prec):
+    # the compression run of test_newton_static_compression with the P+1
+    # point Gauss-Lobatto-Legendre rule, against the oracle with that rule
+    bits = inputs.face_bits(4) | inputs.face_bits(5)
+    p = Pair((3, 3, 3), (1.0, 1.0, 1.0), 3, kind=ob.NODAL, dirichlet=bits, Q=4)
+    G = np.zeros((3, 3))
+    G[2, 2] = -0.1
+    u0 = p.ctx.affine_field([0, 0, 0], G) + p.mask * p.rand(8, 2e-4)
+    ud = p.dev(u0)
+    st = p.ctx.newton_static(p.mat, prec, ud, newton_rtol=1e-8, pcg_rtol=1e-8)
+    ur, hist = osv.newton_static(p.pb, u0, np.zeros_like(u0), 1e-8, 1e-8)
+    assert st["newton_rel"] <= 1e-8
+    assert abs(st["newton"] - sum(1 for h in hist if isinstance(h, tuple))) <= 1
+    assert relerr(p.host(ud), ur) < 1e-7
+
+
+def test_affine_patch_reproduced_with_gll_rule():
+    # every face prescribed by an affine field, a perturbed interior: Newton
+    # recovers the affine field (homogeneous deformation is an equilibrium)
+    bits = sum(inputs.face_bits(f) for f in range(6))
+    p = Pair((2, 2, 2), (1.0, 1.0, 1.0), 4, kind=ob.NODAL, dirichlet=bits, Q=5)
+    G = np.array([[0.05, 0.02, 0.0], [0.01, -0.03, 0.02], [0.0, 0.01, 0.04]])
+    ua = p.ctx.affine_field([0.01, 0.0, -0.02], G)
+    ud = p.dev(ua + p.mask * p.rand(9, 1e-3))
+    st = p.ctx.newton_static(p.mat, FP64, ud, newton_rtol=1e-10, pcg_rtol=1e-10)
+    assert st["newton_rel"] <= 1e-10
+    assert relerr(p.host(ud), ua) < 1e-9
