@@ -653,98 +653,6 @@ def case_quartic(a):
             "time_error_ratios_per_halving": [round(x, 3) for x in rates]}
 
 
-# explicit time steps of the conrod runs of Section 5, per order
-CONROD_DT = {2: 6.06e-6, 3: 6.06e-6, 4: 3.03e-6, 5: 1.51e-6, 6: 1.51e-6, 7: 1.51e-6, 8: 7.58e-7}
-
-
-def case_conrod(a):
-    """Stand-in for the conrod runs of Section 5 (768 hexahedra; the paper's
-    mesh exists only as a figure): a 16x8x6 box of 768 hexahedra, 160 x 80 x 60
-    (element edge 10, in the length unit in which the paper's time steps are
-    stable), E = 500, nu = 0.3, rho = 9.5e-7, face x = 0 clamped (small end),
-    traction (1, 1, 0) sin(pi t / T) on the face x = max (big end),
-    T = 5.454e-3, u0 = v0 = 0.  Explicit central differences with the paper's
-    time step per order and mass PCG to 1e-8; Newmark with dt = 1.515e-5, PCG
-    and Newton to 1e-4.  Modal (ST), SDME-M and SDME-H, P = 2..8: PCG
-    iterations and time per step, speedup t_ST / t_SDME per step (Tables
-    Tab:Conrod_explicit_iterations, Tab:Conrod_explicit_time,
-    Tab:Conrod_implicit_iterations)."""
-    import torch
-
-    from paper_2104_13466_amd import inputs
-    from paper_2104_13466_amd.sdme import FP64, Context
-    E_, nu, rho, T = 500.0, 0.3, 9.5e-7, 5.454e-3
-    lam0, mu0 = inputs.lame(E_, nu)
-    n, L = (16, 8, 6), (160.0, 80.0, 60.0)
-    steps_ex, steps_im = a.conrod_steps, max(2, a.conrod_steps // 2)
-    rows = []
-    for P in range(2, 9):
-        dt = CONROD_DT[P]
-        row = {"P": P, "dt_explicit": dt}
-        for kind in (1, 2, 4):
-            ctx = Context(n, L, P, basis=kind, dirichlet=inputs.face_bits(0))
-            mat = Context.material(torch.full((ctx.E,), mu0, dtype=torch.float64, device="cuda"),
-                                   torch.full((ctx.E,), lam0, dtype=torch.float64, device="cuda"),
-                                   rho)
-            N = 3 * ctx.Nn
-            row["dofs"] = N
-            zero = torch.zeros(N, dtype=torch.float64, device="cuda")
-            if kind == 2:
-                x0 = torch.tensor(inputs.uniform(7, N, -1, 1), device="cuda")
-                lmax = ctx.lambda_max(mat, zero, x0, iters=40, mass_rtol=1e-8)
-                row["dt_explicit_over_critical"] = round(dt * np.sqrt(lmax) / 2.0, 4)
-
-            def load(t, f):
-                f.zero_()
-                ctx.face_traction(1, [1.0, 1.0, 0.0], f, scale=float(np.sin(np.pi * t / T)))
-
-            # explicit: start step, then timed steps
-            us = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(3)]
-            f = torch.zeros_like(zero)
-            load(0.0, f)
-            ctx.explicit_step(mat, FP64, None, us[0], us[1], dt, v0=zero, f_ext=f, mass_rtol=1e-8)
-            its = 0
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(1, steps_ex + 1):
-                load(k * dt, f)
-                st = ctx.explicit_step(mat, FP64, us[(k - 1) % 3], us[k % 3], us[(k + 1) % 3], dt,
-                                       f_ext=f, mass_rtol=1e-8)
-                its += st["mass_iterations"]
-            torch.cuda.synchronize()
-            ex_ms = 1e3 * (time.perf_counter() - t0) / steps_ex
-            # implicit Newmark
-            u, v, acc = (torch.zeros(N, dtype=torch.float64, device="cuda") for _ in range(3))
-            dti = 1.515e-5
-            pits = newton = 0
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(steps_im):
-                load((k + 1) * dti, f)
-                st = ctx.newmark_newton_step(mat, FP64, u, v, acc, f, dti, newton_rtol=1e-4,
-                                             pcg_rtol=1e-4, max_pcg=200000)
-                pits += st["iterations"]
-                newton += st["newton"]
-            torch.cuda.synchronize()
-            im_ms = 1e3 * (time.perf_counter() - t0) / steps_im
-            name = KIND_NAMES[kind]
-            row[name] = {"explicit_pcg_per_step": round(its / steps_ex, 2),
-                         "explicit_ms_per_step": round(ex_ms, 3),
-                         "implicit_pcg_per_step": round(pits / steps_im, 2),
-                         "implicit_newton_per_step": round(newton / steps_im, 2),
-                         "implicit_ms_per_step": round(im_ms, 3)}
-            ctx.close()
-        for b in ("sdme_m", "sdme_h"):
-            row["explicit_speedup_st_over_" + b] = round(
-                row["modal"]["explicit_ms_per_step"] / row[b]["explicit_ms_per_step"], 2)
-            row["implicit_speedup_st_over_" + b] = round(
-                row["modal"]["implicit_ms_per_step"] / row[b]["implicit_ms_per_step"], 2)
-        log("conrod %s" % row)
-        rows.append(row)
-    return {"case": "conrod", "mesh": "16x8x6 hexahedra (768), 160x80x60", "steps_explicit":
-            steps_ex, "steps_implicit": steps_im, "rows": rows}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -764,10 +672,9 @@ def main():
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params",
-                                      "static", "wave", "conrod", "quartic"],
+                                      "static", "wave", "quartic"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
-    ap.add_argument("--conrod-steps", type=int, default=6)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: libsdme has no multi-GPU path (slab partition "
@@ -780,7 +687,7 @@ def main():
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
               "adjoint": case_adjoint, "params": case_params, "static": case_static,
-              "wave": case_wave, "conrod": case_conrod, "quartic": case_quartic}[a.case]
+              "wave": case_wave, "quartic": case_quartic}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)

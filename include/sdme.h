@@ -13,15 +13,16 @@
  *  - Plain C ABI.  Every function returns an int status (SDME_OK = 0 or a
  *    negative SDME_E* code); no exception or abort crosses the boundary.
  *    Arguments are validated on the host before any launch.
- *  - "dev" pointers are device (HBM) pointers owned by the caller; "host"
- *    pointers are host memory owned by the caller.  The library never frees a
- *    caller buffer.  A context allocates one small device block (basis
+ *  - The caller owns all memory; the library allocates and frees no device
+ *    or pinned memory.  "dev" pointers are device (HBM) pointers, "host"
+ *    pointers host memory, both owned by the caller.  A context is a small
+ *    host object (sdme_create / sdme_destroy); its device block (basis
  *    tables, reduction partials and solver scalars, O(number of elements)
- *    bytes) and a few bytes of pinned host memory on the first call that
- *    touches the device, on the device current at that call; both are
- *    released by sdme_destroy.  Large scratch (solver
- *    vectors, linearisation state) is passed in by the caller as a workspace
- *    of at least sdme_workspace_bytes() bytes.
+ *    bytes) and host block (scalars the drivers read back) are allocated by
+ *    the caller at the sizes sdme_context_bytes reports and attached with
+ *    sdme_bind before the first call that touches the device.  Large scratch
+ *    (solver vectors, linearisation state) is passed in by the caller as a
+ *    workspace of at least sdme_workspace_bytes() bytes.
  *  - Vectors are structure-of-arrays [3][Nn]: component c of global slot g at
  *    index c*Nn + g.  The structured slot grid has Nd = nd*P+1 slots per
  *    direction, numbered x fastest: g = (iz*Ny + iy)*Nx + ix.  Element
@@ -120,13 +121,34 @@ typedef struct {
                       /* (mass_shift != 0, Newmark) then return SDME_EINVAL     */
 } sdme_mesh_desc;
 
-/* Create a context for a structured box mesh.  The basis is built on the
- * host (sdme_basis_build) at once; its tables are uploaded to the context's
- * device block by the first device call (host-only queries such as
- * sdme_sizes and sdme_gather_indices never touch the device).  Meshes need
+/* Create a context for a structured box mesh (host only).  The basis is
+ * built on the host (sdme_basis_build) at once; its tables are uploaded to
+ * the caller's device block by sdme_bind (host-only queries such as
+ * sdme_sizes and sdme_gather_indices need no binding).  Meshes need
  * 3*Nn < 2^31.  Errors: SDME_EINVAL, SDME_EEIG. */
 int sdme_create(const sdme_mesh_desc *desc, sdme_ctx **out);
+/* Releases the host object only: the caller frees the blocks it bound, once
+ * the work it queued on them has completed. */
 int sdme_destroy(sdme_ctx *ctx);
+
+/* Sizes of the memory a context needs from the caller: *dev_bytes of device
+ * memory (basis tables of the volume and mass rules in FP64 and FP32, the
+ * Jacobian flag, PCG scalars, per-block reduction partials) and *host_bytes
+ * of host memory (solver scalars copied back by the drivers).  Host-only.
+ * Errors: SDME_EINVAL. */
+int sdme_context_bytes(const sdme_ctx *ctx, size_t *dev_bytes, size_t *host_bytes);
+
+/* Attach caller-owned memory to a context and upload its basis tables:
+ * dev_block (device, at least dev_bytes, 256-byte aligned) is zero-filled by
+ * a kernel and the tables are copied into it with hipMemcpyAsync, both on
+ * stream; host_block (host, at least host_bytes, 8-byte aligned; pinned
+ * memory keeps the drivers' read-backs asynchronous copies) is cleared at
+ * once.  The context keeps both pointers (it does not own them) until it is
+ * destroyed or bound again.  Every entry point that touches the device returns
+ * SDME_EINVAL on a context that was never bound.  Errors: SDME_EINVAL (sizes,
+ * alignment, NULL), SDME_EDEVICE. */
+int sdme_bind(sdme_ctx *ctx, void *dev_block, size_t dev_bytes, void *host_block,
+              size_t host_bytes, void *stream);
 
 /* out[0] = Nn (slots per component), out[1] = E (elements),
  * out[2] = Gauss points (E*Q^3), out[3] = words of linearisation state per

@@ -20,6 +20,14 @@ using namespace sdme;
 #define SDME_FUSED_PAP 1
 #endif
 
+// Offsets of the parts of the context's device block, and its size.
+struct BlockPlan {
+  size_t o_tm64 = 0, o_tm32 = 0, o_t64 = 0, o_t32 = 0, o_flag = 0, o_pcg = 0, o_part = 0,
+         o_cnt = 0, o_res = 0, dev_bytes = 0, host_bytes = 0;
+};
+// Host block: PcgDev[2] at 0, double[16] at 1024, int at 2048.
+constexpr size_t HOST_BLOCK_BYTES = 4096;
+
 struct sdme_ctx {
   sdme_mesh_desc d;
   int P, Q, n;
@@ -34,6 +42,7 @@ struct sdme_ctx {
   unsigned *counter = nullptr;
   double *results = nullptr;  // [16]
   void *host_block = nullptr;
+  BlockPlan plan;
   PcgDev *h_pcg = nullptr;
   double *h_res = nullptr;
   int *h_flag = nullptr;
@@ -46,7 +55,6 @@ struct sdme_ctx {
   double *tabm64 = nullptr;
   float *tabm32 = nullptr;
   std::vector<double> tabm_host;
-  int device = 0;
   bool dev_ready = false;
   // optional per-launch timing of the PCG operator (HIP events on the solve
   // stream): [0] FP64 operator, [1] FP32 operator
@@ -55,6 +63,7 @@ struct sdme_ctx {
   double prof_ms[2] = {0, 0};
   int64_t prof_count[2] = {0, 0};
   std::vector<double> tab_host;
+  std::vector<float> tab32_host, tabm32_host;
 };
 
 namespace {
@@ -370,15 +379,13 @@ size_t lin_bytes(sdme_ctx *c, int prec, bool state32) {
 }  // namespace
 
 
-// Device block (tables, reduction partials, solver scalars) and pinned host
-// scalars, allocated on the first call that touches the device.
-static int ensure_device(sdme_ctx *c) {
-  if (c->dev_ready) return SDME_OK;
+// Layout of the context's device block (tables, reduction partials, solver
+// scalars) and host block (scalars read back by the drivers); both are
+// allocated by the caller (sdme_context_bytes, sdme_bind).
+static void plan_blocks(sdme_ctx *c) {
   const sdme_mesh_desc *d = &c->d;
-  int P = c->P;
-  int64_t E = c->E;
-  int TS = (int)c->tab_host.size();
-  const std::vector<double> &tab = c->tab_host;
+  const int P = c->P;
+  const int TS = (int)c->tab_host.size(), TSM = (int)c->tabm_host.size();
   int nblk = 0;
   for (int q : {c->Q, c->mm64.Q})
     for (int word : {4, 8})
@@ -393,56 +400,26 @@ static int ensure_device(sdme_ctx *c) {
     bytes += (b + 255) & ~(size_t)255;
     return o;
   };
-  const int TSM = (int)c->tabm_host.size();
-  size_t o_tm64 = take(sizeof(double) * TSM), o_tm32 = take(sizeof(float) * TSM);
-  size_t o_t64 = take(sizeof(double) * TS), o_t32 = take(sizeof(float) * TS),
-         o_flag = take(sizeof(int)), o_pcg = take(2 * sizeof(PcgDev)),
-         o_part = take(sizeof(double) * 2 * (size_t)nblk), o_cnt = take(sizeof(unsigned) * 4),
-         o_res = take(sizeof(double) * 16);
-  if (hipGetDevice(&c->device) != hipSuccess || hipMalloc(&c->dev_block, bytes) != hipSuccess)
-    return SDME_EDEVICE;
-  char *base = (char *)c->dev_block;
-  c->tab64 = (double *)(base + o_t64);
-  c->tabm64 = (double *)(base + o_tm64);
-  c->tabm32 = (float *)(base + o_tm32);
-  c->tab32 = (float *)(base + o_t32);
-  c->flag = (int *)(base + o_flag);
-  c->pcg = (PcgDev *)(base + o_pcg);
-  c->partials = (double *)(base + o_part);
-  c->counter = (unsigned *)(base + o_cnt);
-  c->results = (double *)(base + o_res);
-  std::vector<float> tab32(TS), tabm32(TSM);
-  for (int i = 0; i < TS; i++) tab32[i] = (float)tab[i];
-  for (int i = 0; i < TSM; i++) tabm32[i] = (float)c->tabm_host[i];
-  if (hipMemset(c->dev_block, 0, bytes) != hipSuccess ||
-      hipMemcpy(c->tab64, tab.data(), sizeof(double) * TS, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->tab32, tab32.data(), sizeof(float) * TS, hipMemcpyHostToDevice) != hipSuccess ||
-      (TSM && (hipMemcpy(c->tabm64, c->tabm_host.data(), sizeof(double) * TSM,
-                         hipMemcpyHostToDevice) != hipSuccess ||
-               hipMemcpy(c->tabm32, tabm32.data(), sizeof(float) * TSM, hipMemcpyHostToDevice) !=
-                   hipSuccess)) ||
-      hipHostMalloc(&c->host_block, 4096, hipHostMallocDefault) != hipSuccess) {
-    hipFree(c->dev_block);
-    c->dev_block = nullptr;
-    return SDME_EDEVICE;
-  }
-  c->h_pcg = (PcgDev *)c->host_block;
-  c->h_res = (double *)((char *)c->host_block + 1024);
-  c->h_flag = (int *)((char *)c->host_block + 2048);
-  c->m64.tab = c->tab64;
-  c->m64.flag = c->flag;
-  c->m32.tab = c->tab32;
-  c->m32.flag = c->flag;
-  c->mm64 = c->m64;
-  c->mm32 = c->m32;
-  if (TSM) {
-    c->mm64.Q = c->mm32.Q = c->P + 1;
-    c->mm64.tab = c->tabm64;
-    c->mm32.tab = c->tabm32;
-  }
-  c->dev_ready = true;
-  return SDME_OK;
+  BlockPlan &b = c->plan;
+  b.o_tm64 = take(sizeof(double) * TSM);
+  b.o_tm32 = take(sizeof(float) * TSM);
+  b.o_t64 = take(sizeof(double) * TS);
+  b.o_t32 = take(sizeof(float) * TS);
+  b.o_flag = take(sizeof(int));
+  b.o_pcg = take(2 * sizeof(PcgDev));
+  b.o_part = take(sizeof(double) * 2 * (size_t)nblk);
+  b.o_cnt = take(sizeof(unsigned) * 4);
+  b.o_res = take(sizeof(double) * 16);
+  b.dev_bytes = bytes;
+  b.host_bytes = HOST_BLOCK_BYTES;
+  c->tab32_host.resize(TS);
+  for (int i = 0; i < TS; i++) c->tab32_host[i] = (float)c->tab_host[i];
+  c->tabm32_host.resize(TSM);
+  for (int i = 0; i < TSM; i++) c->tabm32_host[i] = (float)c->tabm_host[i];
 }
+
+// Every entry point that touches the device requires bound memory.
+static int ensure_device(sdme_ctx *c) { return c->dev_ready ? SDME_OK : SDME_EINVAL; }
 
 // ======================================================================= API
 extern "C" const char *sdme_status_string(int s) {
@@ -542,7 +519,68 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   f.detJ = (float)m.detJ;
   f.tab = nullptr;
   f.flag = nullptr;
+  c->mm64 = c->m64;
+  c->mm32 = c->m32;
+  if (!c->tabm_host.empty()) c->mm64.Q = c->mm32.Q = c->P + 1;
+  plan_blocks(c);
   *out = c;
+  return SDME_OK;
+}
+
+extern "C" int sdme_context_bytes(const sdme_ctx *c, size_t *dev_bytes, size_t *host_bytes) {
+  if (!c || !dev_bytes || !host_bytes) return SDME_EINVAL;
+  *dev_bytes = c->plan.dev_bytes;
+  *host_bytes = c->plan.host_bytes;
+  return SDME_OK;
+}
+
+extern "C" int sdme_bind(sdme_ctx *c, void *dev_block, size_t dev_bytes, void *host_block,
+                         size_t host_bytes, void *stream) {
+  if (!c || !dev_block || !host_block || dev_bytes < c->plan.dev_bytes ||
+      host_bytes < c->plan.host_bytes || ((uintptr_t)dev_block & 255) != 0 ||
+      ((uintptr_t)host_block & 7) != 0)
+    return SDME_EINVAL;
+  const BlockPlan &b = c->plan;
+  hipStream_t st = S(stream);
+  char *base = (char *)dev_block;
+  c->dev_block = dev_block;
+  c->host_block = host_block;
+  c->tab64 = (double *)(base + b.o_t64);
+  c->tabm64 = (double *)(base + b.o_tm64);
+  c->tabm32 = (float *)(base + b.o_tm32);
+  c->tab32 = (float *)(base + b.o_t32);
+  c->flag = (int *)(base + b.o_flag);
+  c->pcg = (PcgDev *)(base + b.o_pcg);
+  c->partials = (double *)(base + b.o_part);
+  c->counter = (unsigned *)(base + b.o_cnt);
+  c->results = (double *)(base + b.o_res);
+  c->h_pcg = (PcgDev *)host_block;
+  c->h_res = (double *)((char *)host_block + 1024);
+  c->h_flag = (int *)((char *)host_block + 2048);
+  std::memset(host_block, 0, b.host_bytes);
+  const size_t TS = c->tab_host.size(), TSM = c->tabm_host.size();
+  // zero fill by a kernel (no memset node, so a caller may capture the
+  // binding), then the tables, both on the caller's stream
+  if (launch_fill<double>((double *)dev_block, 0.0, (int64_t)(b.dev_bytes / 8), st) ||
+      hipMemcpyAsync(c->tab64, c->tab_host.data(), sizeof(double) * TS, hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(c->tab32, c->tab32_host.data(), sizeof(float) * TS, hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      (TSM && (hipMemcpyAsync(c->tabm64, c->tabm_host.data(), sizeof(double) * TSM,
+                              hipMemcpyHostToDevice, st) != hipSuccess ||
+               hipMemcpyAsync(c->tabm32, c->tabm32_host.data(), sizeof(float) * TSM,
+                              hipMemcpyHostToDevice, st) != hipSuccess))) {
+    c->dev_ready = false;
+    return SDME_EDEVICE;
+  }
+  c->m64.tab = c->tab64;
+  c->m64.flag = c->flag;
+  c->m32.tab = c->tab32;
+  c->m32.flag = c->flag;
+  c->mm64.flag = c->mm32.flag = c->flag;
+  c->mm64.tab = TSM ? c->tabm64 : c->tab64;
+  c->mm32.tab = TSM ? c->tabm32 : c->tab32;
+  c->dev_ready = true;
   return SDME_OK;
 }
 
@@ -570,15 +608,7 @@ extern "C" int sdme_profile(sdme_ctx *c, int enable, double ms_out[2], int64_t c
 extern "C" int sdme_destroy(sdme_ctx *c) {
   if (!c) return SDME_EINVAL;
   for (auto &e : c->ev) hipEventDestroy(e);
-  if (c->dev_ready) {
-    int dev = 0;
-    hipGetDevice(&dev);
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
-    if (c->dev_block) hipFree(c->dev_block);
-    if (c->host_block) hipHostFree(c->host_block);
-    hipSetDevice(dev);
-  }
+  // the device and host blocks belong to the caller
   delete c;
   return SDME_OK;
 }

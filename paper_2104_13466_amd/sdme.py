@@ -66,6 +66,8 @@ SIGNATURES = {
     "sdme_basis_eval": ([_i, _i, _d, _d, _i, _dp, _dp, _dp], _i),
     "sdme_create": ([ctypes.POINTER(MeshDesc), ctypes.POINTER(_vp)], _i),
     "sdme_destroy": ([_vp], _i),
+    "sdme_context_bytes": ([_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)], _i),
+    "sdme_bind": ([_vp, _vp, _sz, _vp, _sz, _vp], _i),
     "sdme_sizes": ([_vp, ctypes.POINTER(_i64)], _i),
     "sdme_gather_indices": ([_vp, ctypes.POINTER(ctypes.c_int32)], _i),
     "sdme_dirichlet_flags": ([_vp, ctypes.POINTER(ctypes.c_uint8)], _i),
@@ -165,6 +167,39 @@ def _stream(stream):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _dtype(prec):
+    import torch
+    if prec == FP64:
+        return torch.float64
+    if prec == FP32:
+        return torch.float32
+    raise ValueError("prec must be FP64 (0) or FP32 (1), got %r" % (prec,))
+
+
+def check_dev(t, dtype, n, name, at_least=False, optional=False):
+    """Validate a device argument before it reaches the C ABI: a contiguous
+    torch tensor on the HIP device, of the element type the call computes in
+    and of the length the call reads or writes (n elements; at least n with
+    at_least).  Raises ValueError on any mismatch."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError("%s: a device tensor is required" % name)
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s: expected a torch tensor, got %s" % (name, type(t).__name__))
+    if t.dtype != dtype:
+        raise ValueError("%s: expected dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s: tensor must be contiguous" % name)
+    if (t.numel() < n) if at_least else (t.numel() != n):
+        raise ValueError("%s: expected %s%d elements, got %d"
+                         % (name, "at least " if at_least else "", n, t.numel()))
+    if t.device.type != "cuda":
+        raise ValueError("%s: expected a tensor on the HIP device, got %s" % (name, t.device))
+    return ctypes.c_void_p(t.data_ptr())
+
+
 class Context:
     """Structured box mesh + basis (sdme_create / sdme_destroy)."""
 
@@ -190,7 +225,49 @@ class Context:
         sz = (ctypes.c_int64 * 4)()
         _chk(self.L.sdme_sizes(h, sz), "sizes")
         self.Nn, self.E, self.nqp, self.state_words = (int(v) for v in sz)
+        self.N = 3 * self.Nn
         self._ws = None
+        self._blocks = None
+
+    # ------------------------------------------------------- caller memory
+    def context_bytes(self):
+        """(device bytes, host bytes) the context needs (sdme_context_bytes)."""
+        db, hb = ctypes.c_size_t(), ctypes.c_size_t()
+        _chk(self.L.sdme_context_bytes(self.handle, ctypes.byref(db), ctypes.byref(hb)),
+             "context_bytes")
+        return db.value, hb.value
+
+    def _st(self, stream):
+        """The stream argument of a device call; binds the context's device
+        block (torch device memory) and pinned host block on first use."""
+        st = _stream(stream)
+        if self._blocks is None:
+            import torch
+            db, hb = self.context_bytes()
+            dev = torch.empty(max(db, 256), dtype=torch.uint8, device="cuda")
+            host = torch.empty(max(hb, 64), dtype=torch.uint8, pin_memory=True)
+            _chk(self.L.sdme_bind(self.handle, ctypes.c_void_p(dev.data_ptr()), dev.numel(),
+                                  ctypes.c_void_p(host.data_ptr()), host.numel(), st), "bind")
+            self._blocks = (dev, host)
+        return st
+
+    # argument checks (before any call into the library)
+    def _v(self, t, prec, name, optional=False):
+        return check_dev(t, _dtype(prec), self.N, name, optional=optional)
+
+    def _state(self, t, prec, name="state", optional=False):
+        return check_dev(t, _dtype(prec), self.nqp * self.state_words, name, optional=optional)
+
+    def _e(self, t, name):
+        import torch
+        return check_dev(t, torch.float64, self.E, name)
+
+    def _mat(self, mat):
+        if not isinstance(mat, Material) or not hasattr(mat, "_keep"):
+            raise ValueError("material: build it with Context.material(mu, lam, rho)")
+        self._e(mat._keep[0], "material.mu")
+        self._e(mat._keep[1], "material.lam")
+        return ctypes.byref(mat)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -242,6 +319,11 @@ class Context:
 
     @staticmethod
     def material(mu, lam, rho):
+        """Per-element Lame parameters (device float64 tensors of length E;
+        the length is checked by each call) and the density."""
+        import torch
+        check_dev(mu, torch.float64, 0, "material.mu", at_least=True)
+        check_dev(lam, torch.float64, 0, "material.lam", at_least=True)
         m = Material()
         m.mu = mu.data_ptr()
         m.lam = lam.data_ptr()
@@ -251,44 +333,51 @@ class Context:
 
     # -------------------------------------------------------------- operators
     def internal_force(self, mat, prec, u, R, state=None, flags=0, stream=None):
-        _chk(self.L.sdme_internal_force(self.handle, ctypes.byref(mat), prec, _ptr(u), _ptr(R),
-                                        _ptr(state), flags, _stream(stream)), "internal_force")
+        args = (self._mat(mat), prec, self._v(u, prec, "u"), self._v(R, prec, "R"),
+                self._state(state, prec, optional=True), flags)
+        _chk(self.L.sdme_internal_force(self.handle, *args, self._st(stream)), "internal_force")
 
     def linearize(self, mat, prec, u, state, flags=0, stream=None):
-        _chk(self.L.sdme_linearize(self.handle, ctypes.byref(mat), prec, _ptr(u), _ptr(state), flags,
-                                   _stream(stream)), "linearize")
+        args = (self._mat(mat), prec, self._v(u, prec, "u"), self._state(state, prec), flags)
+        _chk(self.L.sdme_linearize(self.handle, *args, self._st(stream)), "linearize")
 
     def tangent_apply(self, mat, prec, v, y, u_lin=None, state=None, mass_shift=0.0, flags=0,
                       stream=None):
-        _chk(self.L.sdme_tangent_apply(self.handle, ctypes.byref(mat), prec, _ptr(u_lin),
-                                       _ptr(state), mass_shift, _ptr(v), _ptr(y), flags,
-                                       _stream(stream)), "tangent_apply")
+        if (u_lin is None) == (state is None):
+            raise ValueError("tangent_apply: pass exactly one of u_lin and state")
+        args = (self._mat(mat), prec, self._v(u_lin, prec, "u_lin", optional=True),
+                self._state(state, prec, optional=True), mass_shift, self._v(v, prec, "v"),
+                self._v(y, prec, "y"), flags)
+        _chk(self.L.sdme_tangent_apply(self.handle, *args, self._st(stream)), "tangent_apply")
 
     def mass_apply(self, rho, prec, v, y, flags=0, stream=None):
-        _chk(self.L.sdme_mass_apply(self.handle, rho, prec, _ptr(v), _ptr(y), flags,
-                                    _stream(stream)), "mass_apply")
+        args = (rho, prec, self._v(v, prec, "v"), self._v(y, prec, "y"), flags)
+        _chk(self.L.sdme_mass_apply(self.handle, *args, self._st(stream)), "mass_apply")
 
     def jacobi_diag(self, mat, prec, state, mass_shift, d, flags=0, stream=None):
-        _chk(self.L.sdme_jacobi_diag(self.handle, ctypes.byref(mat), prec, _ptr(state), mass_shift,
-                                     _ptr(d), flags, _stream(stream)), "jacobi_diag")
+        args = (self._mat(mat), prec, self._state(state, prec, optional=True), mass_shift,
+                self._v(d, prec, "d"), flags)
+        _chk(self.L.sdme_jacobi_diag(self.handle, *args, self._st(stream)), "jacobi_diag")
 
     def strain_energy(self, mat, u, stream=None):
         out = ctypes.c_double()
-        _chk(self.L.sdme_strain_energy(self.handle, ctypes.byref(mat), _ptr(u), ctypes.byref(out),
-                                       _stream(stream)), "strain_energy")
+        args = (self._mat(mat), self._v(u, FP64, "u"), ctypes.byref(out))
+        _chk(self.L.sdme_strain_energy(self.handle, *args, self._st(stream)), "strain_energy")
         return out.value
 
     def face_traction(self, face, t, f, scale=1.0, stream=None):
         t = np.ascontiguousarray(t, dtype=np.float64)
-        _chk(self.L.sdme_face_traction(self.handle, face, _hp(t), scale, _ptr(f), _stream(stream)),
-             "face_traction")
+        if t.size != 3:
+            raise ValueError("face_traction: t must hold 3 values")
+        args = (face, _hp(t), scale, self._v(f, FP64, "f"))
+        _chk(self.L.sdme_face_traction(self.handle, *args, self._st(stream)), "face_traction")
 
     def penalty_plane(self, eps, z0, u, f, energy=False, stream=None):
         c = Contact(eps, z0)
         e = ctypes.c_double()
-        _chk(self.L.sdme_penalty_plane(self.handle, ctypes.byref(c), _ptr(u), _ptr(f),
-                                       ctypes.byref(e) if energy else None, _stream(stream)),
-             "penalty_plane")
+        args = (ctypes.byref(c), self._v(u, FP64, "u"), self._v(f, FP64, "f"),
+                ctypes.byref(e) if energy else None)
+        _chk(self.L.sdme_penalty_plane(self.handle, *args, self._st(stream)), "penalty_plane")
         return e.value if energy else None
 
     # ------------------------------------------ loads at quadrature points
@@ -310,28 +399,41 @@ class Context:
         return out
 
     def body_load(self, b, f, stream=None):
-        _chk(self.L.sdme_body_load(self.handle, _ptr(b), _ptr(f), _stream(stream)), "body_load")
+        import torch
+        args = (check_dev(b, torch.float64, 3 * self.E * self.Q ** 3, "b"),
+                self._v(f, FP64, "f"))
+        _chk(self.L.sdme_body_load(self.handle, *args, self._st(stream)), "body_load")
 
     def face_load(self, face, t, f, stream=None):
-        _chk(self.L.sdme_face_load(self.handle, face, _ptr(t), _ptr(f), _stream(stream)),
-             "face_load")
+        import torch
+        if not 0 <= face < 6:
+            raise ValueError("face_load: face must be 0..5")
+        nt = 3 * self.face_elements(face) * (self.P + 1) ** 2
+        args = (face, check_dev(t, torch.float64, nt, "t"), self._v(f, FP64, "f"))
+        _chk(self.L.sdme_face_load(self.handle, *args, self._st(stream)), "face_load")
 
     def l2_error(self, u, g, stream=None):
         """L2 norms over the box of (u_h - g) per component; g at the volume
         Gauss points (3, E, Q^3)."""
+        import torch
         out = np.zeros(3)
-        _chk(self.L.sdme_l2_error(self.handle, _ptr(u), _ptr(g), _hp(out), _stream(stream)),
-             "l2_error")
+        args = (self._v(u, FP64, "u"), check_dev(g, torch.float64, 3 * self.E * self.Q ** 3, "g"),
+                _hp(out))
+        _chk(self.L.sdme_l2_error(self.handle, *args, self._st(stream)), "l2_error")
         return out
 
     def material_grad_accumulate(self, u, w, scale, g_mu, g_lam, stream=None):
-        _chk(self.L.sdme_material_grad_accumulate(self.handle, _ptr(u), _ptr(w), scale, _ptr(g_mu),
-                                                  _ptr(g_lam), _stream(stream)),
+        args = (self._v(u, FP64, "u"), self._v(w, FP64, "w"), scale, self._e(g_mu, "g_mu"),
+                self._e(g_lam, "g_lam"))
+        _chk(self.L.sdme_material_grad_accumulate(self.handle, *args, self._st(stream)),
              "material_grad_accumulate")
 
     def axpby(self, alpha, x, beta, y, stream=None):
-        _chk(self.L.sdme_axpby(self.handle, y.numel(), alpha, _ptr(x), beta, _ptr(y),
-                               _stream(stream)), "axpby")
+        import torch
+        n = y.numel() if y is not None else 0
+        args = (n, alpha, check_dev(x, torch.float64, n, "x"), beta,
+                check_dev(y, torch.float64, n, "y"))
+        _chk(self.L.sdme_axpby(self.handle, args[0], *args[1:], self._st(stream)), "axpby")
 
     def profile(self, enable):
         """Return {fp64_ms, fp64_count, fp32_ms, fp32_count} accumulated since
@@ -343,18 +445,20 @@ class Context:
 
     def misfit(self, u, target, lam_out, stream=None):
         J = ctypes.c_double()
-        _chk(self.L.sdme_misfit(self.handle, _ptr(u), _ptr(target), _ptr(lam_out), ctypes.byref(J),
-                                _stream(stream)), "misfit")
+        args = (self._v(u, FP64, "u"), self._v(target, FP64, "target"),
+                self._v(lam_out, FP64, "lam_out"), ctypes.byref(J))
+        _chk(self.L.sdme_misfit(self.handle, *args, self._st(stream)), "misfit")
         return J.value
 
     # ---------------------------------------------------------------- solvers
     def jacobi_pcg(self, mat, prec, b, x, u_lin=None, mass_shift=0.0, mass_only=False, rtol=1e-8,
                    maxit=100000, inner_rtol=1e-2, stream=None, check=True):
         st = Stats()
+        args = (self._mat(mat), prec, self._v(u_lin, FP64, "u_lin", optional=mass_only),
+                mass_shift, 1 if mass_only else 0, self._v(b, FP64, "b"), self._v(x, FP64, "x"),
+                rtol, maxit, inner_rtol, ctypes.byref(st))
         ws, nb = self._wsargs(OP_PCG, prec)
-        rc = self.L.sdme_jacobi_pcg(self.handle, ctypes.byref(mat), prec, _ptr(u_lin), mass_shift,
-                                    1 if mass_only else 0, _ptr(b), _ptr(x), rtol, maxit,
-                                    inner_rtol, ctypes.byref(st), ws, nb, _stream(stream))
+        rc = self.L.sdme_jacobi_pcg(self.handle, *args, ws, nb, self._st(stream))
         if check:
             _chk(rc, "jacobi_pcg")
         return st.as_dict()
@@ -362,59 +466,68 @@ class Context:
     def newton_static(self, mat, prec, u, f_ext=None, newton_rtol=1e-8, pcg_rtol=1e-8,
                       max_newton=20, max_pcg=100000, stream=None):
         st = Stats()
+        args = (self._mat(mat), prec, self._v(u, FP64, "u"),
+                self._v(f_ext, FP64, "f_ext", optional=True), newton_rtol, pcg_rtol, max_newton,
+                max_pcg, ctypes.byref(st))
         ws, nb = self._wsargs(OP_NEWTON, prec)
-        _chk(self.L.sdme_newton_static(self.handle, ctypes.byref(mat), prec, _ptr(u), _ptr(f_ext),
-                                       newton_rtol, pcg_rtol, max_newton, max_pcg, ctypes.byref(st),
-                                       ws, nb, _stream(stream)), "newton_static")
+        _chk(self.L.sdme_newton_static(self.handle, *args, ws, nb, self._st(stream)),
+             "newton_static")
         return st.as_dict()
 
     def newmark_newton_step(self, mat, prec, u, v, a, f_next, dt, beta=0.25, gamma=0.5,
                             newton_rtol=1e-8, pcg_rtol=1e-8, max_newton=20, max_pcg=100000,
                             stream=None):
         st = Stats()
+        args = (self._mat(mat), prec, self._v(u, FP64, "u"), self._v(v, FP64, "v"),
+                self._v(a, FP64, "a"), self._v(f_next, FP64, "f_next", optional=True), dt, beta,
+                gamma, newton_rtol, pcg_rtol, max_newton, max_pcg, ctypes.byref(st))
         ws, nb = self._wsargs(OP_NEWMARK, prec)
-        _chk(self.L.sdme_newmark_newton_step(self.handle, ctypes.byref(mat), prec, _ptr(u), _ptr(v),
-                                             _ptr(a), _ptr(f_next), dt, beta, gamma, newton_rtol,
-                                             pcg_rtol, max_newton, max_pcg, ctypes.byref(st), ws,
-                                             nb, _stream(stream)), "newmark_newton_step")
+        _chk(self.L.sdme_newmark_newton_step(self.handle, *args, ws, nb, self._st(stream)),
+             "newmark_newton_step")
         return st.as_dict()
 
     def explicit_step(self, mat, prec_force, u_prev, u_cur, u_next, dt, v0=None, f_ext=None,
                       contact=None, mass_rtol=1e-10, stream=None):
         st = Stats()
-        ws, nb = self._wsargs(OP_EXPLICIT, FP64)
+        _dtype(prec_force)
         c = None if contact is None else ctypes.byref(Contact(*contact))
-        _chk(self.L.sdme_explicit_step(self.handle, ctypes.byref(mat), prec_force, _ptr(u_prev),
-                                       _ptr(u_cur), _ptr(u_next), _ptr(v0), _ptr(f_ext), dt, c,
-                                       mass_rtol, ctypes.byref(st), ws, nb, _stream(stream)),
+        args = (self._mat(mat), prec_force, self._v(u_prev, FP64, "u_prev", optional=True),
+                self._v(u_cur, FP64, "u_cur"), self._v(u_next, FP64, "u_next"),
+                self._v(v0, FP64, "v0", optional=True), self._v(f_ext, FP64, "f_ext", optional=True),
+                dt, c, mass_rtol, ctypes.byref(st))
+        ws, nb = self._wsargs(OP_EXPLICIT, FP64)
+        _chk(self.L.sdme_explicit_step(self.handle, *args, ws, nb, self._st(stream)),
              "explicit_step")
         return st.as_dict()
 
     def energies(self, mat, u_prev, u_cur, u_next, dt, contact=None, stream=None):
         out = (ctypes.c_double * 3)()
-        ws, nb = self._wsargs(OP_EXPLICIT, FP64)
         c = None if contact is None else ctypes.byref(Contact(*contact))
-        _chk(self.L.sdme_energies(self.handle, ctypes.byref(mat), _ptr(u_prev), _ptr(u_cur),
-                                  _ptr(u_next), dt, c, out, ws, nb, _stream(stream)), "energies")
+        args = (self._mat(mat), self._v(u_prev, FP64, "u_prev"), self._v(u_cur, FP64, "u_cur"),
+                self._v(u_next, FP64, "u_next"), dt, c, out)
+        ws, nb = self._wsargs(OP_EXPLICIT, FP64)
+        _chk(self.L.sdme_energies(self.handle, *args, ws, nb, self._st(stream)), "energies")
         return tuple(out)
 
     def lambda_max(self, mat, u_lin, x0, iters=50, contact=None, mass_rtol=1e-10, stream=None):
         lam = ctypes.c_double()
+        c = None if contact is None else ctypes.byref(Contact(*contact))
+        args = (self._mat(mat), self._v(u_lin, FP64, "u_lin"), c, self._v(x0, FP64, "x0"), iters,
+                mass_rtol, ctypes.byref(lam))
         nb = self.workspace_bytes(OP_EXPLICIT, FP64) + self.nqp * 80 + 4096
         ws = self.workspace(nb)
-        c = None if contact is None else ctypes.byref(Contact(*contact))
-        _chk(self.L.sdme_lambda_max(self.handle, ctypes.byref(mat), _ptr(u_lin), c, _ptr(x0), iters,
-                                    mass_rtol, ctypes.byref(lam), ctypes.c_void_p(ws.data_ptr()),
-                                    ctypes.c_size_t(ws.numel()), _stream(stream)), "lambda_max")
+        _chk(self.L.sdme_lambda_max(self.handle, *args, ctypes.c_void_p(ws.data_ptr()),
+                                    ctypes.c_size_t(ws.numel()), self._st(stream)), "lambda_max")
         return lam.value
 
     def explicit_adjoint_step(self, mat, u_n, lam_next, lam_next2, lam_out, dt, first, g_mu, g_lam,
                               mass_rtol=1e-12, stream=None):
         st = Stats()
+        args = (self._mat(mat), self._v(u_n, FP64, "u_n"), self._v(lam_next, FP64, "lam_next"),
+                self._v(lam_next2, FP64, "lam_next2", optional=True),
+                self._v(lam_out, FP64, "lam_out", optional=True), dt, 1 if first else 0, mass_rtol,
+                self._e(g_mu, "g_mu"), self._e(g_lam, "g_lam"), ctypes.byref(st))
         ws, nb = self._wsargs(OP_ADJOINT, FP64)
-        _chk(self.L.sdme_explicit_adjoint_step(self.handle, ctypes.byref(mat), _ptr(u_n),
-                                               _ptr(lam_next), _ptr(lam_next2), _ptr(lam_out), dt,
-                                               1 if first else 0, mass_rtol, _ptr(g_mu),
-                                               _ptr(g_lam), ctypes.byref(st), ws, nb,
-                                               _stream(stream)), "explicit_adjoint_step")
+        _chk(self.L.sdme_explicit_adjoint_step(self.handle, *args, ws, nb, self._st(stream)),
+             "explicit_adjoint_step")
         return st.as_dict()

@@ -44,6 +44,30 @@ def test_basis_matches_oracle(kind, P):
         assert np.allclose(t["lambda_s"], b.lambda_s, rtol=1e-12)
 
 
+@pytest.mark.parametrize("kind,k,lam_h", [(ob.SDME_M, 0.0, 100.0), (ob.SDME_M, 1.0, 100.0),
+                                           (ob.SDME_K, 0.0, 100.0), (ob.SDME_K, 1.0, 100.0),
+                                           (ob.SDME_H, 0.0, 1.0), (ob.SDME_H, 1.0, 400.0),
+                                           (ob.SDME_H, 0.5, 1.0), (ob.SDME_H, 0.5, 400.0)])
+@pytest.mark.parametrize("P", [2, 4, 6, 8])
+def test_basis_parameters_match_oracle(kind, k, lam_h, P):
+    # the SD exponent k (Eqs. Y, ParametroK) and the SDME-H weight lambda
+    # (Eqs. EffectiveStiffness_lambda, alphaKN) away from the paper's defaults
+    Q = P + 2
+    t = sdme.basis_build(P, Q, kind, k, lam_h)
+    b, x, w, B, D = ob.build(P, Q, kind, k=k, lam=lam_h)
+    sc = max(1.0, np.abs(D).max())
+    assert np.abs(t["B"] - B).max() < 1e-11 * max(1.0, np.abs(B).max())
+    assert np.abs(t["D"] - D).max() < 1e-11 * sc
+    assert np.abs(t["M1"] - b.M1).max() < 1e-12 * max(1.0, np.abs(b.M1).max())
+    assert np.abs(t["K1"] - b.K1).max() < 1e-11 * max(1.0, np.abs(b.K1).max())
+    assert np.allclose(t["lambda_s"], b.lambda_s, rtol=1e-12)
+    # the parameter reaches the tables: the internal blocks scale as
+    # Lambda^-k (mass) and Lambda^(1-k) (stiffness)
+    lm = np.asarray(b.lambda_s)
+    assert np.allclose(np.diag(t["M1"])[1:P], lm ** (-k), rtol=1e-10)
+    assert np.allclose(np.diag(t["K1"])[1:P], lm ** (1.0 - k), rtol=1e-10)
+
+
 def test_basis_eval_matches_oracle():
     pts = np.linspace(-1, 1, 23)
     V, dV = sdme.basis_eval(6, ob.SDME_H, pts)
@@ -145,3 +169,84 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_context_bytes_and_bind_checks():
+    # the caller allocates the context's memory: a size query, then sdme_bind
+    # with blocks at least that large (256-byte aligned device block);
+    # anything else is refused before the device is touched, and device
+    # entry points refuse a context that was never bound
+    import ctypes
+    c = sdme.Context((5, 2, 2), (1.0, 1.0, 1.0), 3)
+    db, hb = c.context_bytes()
+    assert db > 0 and db % 256 == 0 and hb >= 2048 + 4
+    # tables (volume rule, FP64 + FP32) and per-block partials are inside
+    n, Q = 4, 5
+    assert db >= 12 * (5 * Q * n + Q + n * n + n)
+    big = sdme.Context((40, 60, 60), (1.0, 1.0, 1.0), 3)
+    assert big.context_bytes()[0] > db  # partials grow with the block count
+    big.close()
+    L, h = c.L, c.handle
+    p = ctypes.c_void_p(4096)
+    assert L.sdme_bind(h, None, db, p, hb, None) == -1
+    assert L.sdme_bind(h, p, db, None, hb, None) == -1
+    assert L.sdme_bind(h, p, db - 256, p, hb, None) == -1
+    assert L.sdme_bind(h, p, db, p, hb - 1, None) == -1
+    assert L.sdme_bind(h, ctypes.c_void_p(4096 + 64), db, p, hb, None) == -1
+    out_d, out_h = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.sdme_context_bytes(None, ctypes.byref(out_d), ctypes.byref(out_h)) == -1
+    assert L.sdme_context_bytes(h, None, ctypes.byref(out_h)) == -1
+    # unbound: every device entry point returns SDME_EINVAL
+    assert L.sdme_mass_apply(h, 1.0, 0, p, p, 0, None) == -1
+    m = sdme.Material()
+    m.mu, m.lam, m.rho = 8, 8, 1.0
+    assert L.sdme_internal_force(h, ctypes.byref(m), 0, p, p, None, 0, None) == -1
+    c.close()
+
+
+def test_binding_validates_device_arguments():
+    # dtype against prec, contiguity and length are checked in the binding
+    # before any call into the library (then the device: CPU tensors with
+    # everything else right are refused as not on the HIP device)
+    import torch
+    c = sdme.Context((3, 2, 1), (1.0, 1.0, 1.0), 2)
+    N = 3 * c.Nn
+    d64 = torch.zeros(N, dtype=torch.float64)
+    d32 = torch.zeros(N, dtype=torch.float32)
+    mu = torch.ones(c.E, dtype=torch.float64)
+    with pytest.raises(ValueError, match="HIP device"):
+        sdme.Context.material(mu, mu, 1.0)
+    with pytest.raises(ValueError, match="dtype"):
+        sdme.Context.material(mu.float(), mu, 1.0)
+    m = sdme.Material()
+    m._keep = (mu, mu)
+    with pytest.raises(ValueError, match="dtype"):
+        c.mass_apply(1.0, sdme.FP64, d32, d64)
+    with pytest.raises(ValueError, match="dtype"):
+        c.mass_apply(1.0, sdme.FP32, d64, d32)
+    with pytest.raises(ValueError, match="elements"):
+        c.mass_apply(1.0, sdme.FP64, d64[:-1], d64)
+    with pytest.raises(ValueError, match="contiguous"):
+        c.mass_apply(1.0, sdme.FP64, torch.zeros(2 * N, dtype=torch.float64)[::2], d64)
+    with pytest.raises(ValueError, match="HIP device"):
+        c.mass_apply(1.0, sdme.FP64, d64, d64)
+    with pytest.raises(ValueError, match="prec"):
+        c.mass_apply(1.0, 7, d64, d64)
+    # the per-call length rules: state [E][10][Q^3], per-element arrays [E]
+    with pytest.raises(ValueError, match="elements"):
+        c._state(torch.zeros(c.nqp * 9, dtype=torch.float64), sdme.FP64)
+    with pytest.raises(ValueError, match="dtype"):
+        c._state(torch.zeros(c.nqp * 10, dtype=torch.float64), sdme.FP32)
+    with pytest.raises(ValueError, match="g_mu"):
+        c._e(mu[:-1], "g_mu")
+    with pytest.raises(ValueError, match="material"):
+        c._mat(sdme.Material())  # not built by Context.material
+    bad = sdme.Material()
+    bad._keep = (mu[:-1], mu)
+    with pytest.raises(ValueError, match="material.mu"):
+        c._mat(bad)
+    with pytest.raises(ValueError, match="exactly one"):
+        c.tangent_apply(m, sdme.FP64, d64, d64)
+    # nothing was bound: no device memory was requested by any of these
+    assert c._blocks is None
+    c.close()

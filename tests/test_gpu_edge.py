@@ -110,3 +110,83 @@ def test_zero_right_hand_side(prec):
     s = p.ctx.jacobi_pcg(p.mat, prec, p.zeros(), x, u_lin=p.dev(p.mask * p.rand(17, 1e-3)))
     assert s["iterations"] == 0 and s["rel_residual"] == 0.0
     assert np.abs(p.host(x)).max() == 0.0
+
+
+# Status codes of the C ABI forced from the host: each run ends normally on
+# the device and reports its condition as a return value.
+def test_status_inverted_element_with_check_jac():
+    from paper_2104_13466_amd.sdme import CHECK_JAC, SdmeError
+    p = Pair((4, 2, 1), (1.0, 0.5, 0.5), 3, kind=ob.SDME_H, dirichlet=inputs.face_bits(0))
+    # F = diag(-0.5, 1, 1): every Gauss point has det F < 0
+    u = p.ctx.affine_field([0.0, 0.0, 0.0], np.diag([-1.5, 0.0, 0.0]))
+    ud = p.dev(u)
+    R = p.zeros()
+    with pytest.raises(SdmeError) as e:
+        p.ctx.internal_force(p.mat, FP64, ud, R, flags=CHECK_JAC)
+    assert e.value.code == -5
+    st = p.empty_state()
+    with pytest.raises(SdmeError) as e:
+        p.ctx.linearize(p.mat, FP64, ud, st, flags=CHECK_JAC)
+    assert e.value.code == -5
+    y = p.zeros()
+    with pytest.raises(SdmeError) as e:
+        p.ctx.tangent_apply(p.mat, FP64, p.zeros(), y, u_lin=ud, flags=CHECK_JAC)
+    assert e.value.code == -5
+    s = p.ctx.jacobi_pcg(p.mat, FP64, p.dev(inputs.uniform(3, p.N, -1, 1)), p.zeros(), u_lin=ud,
+                         check=False)
+    assert s["status"] == -5
+    # the flag is cleared by the next checked call: a valid state passes
+    p.ctx.internal_force(p.mat, FP64, p.dev(p.mask * p.rand(4, 1e-3)), R, flags=CHECK_JAC)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_status_iteration_limit(prec):
+    p = Pair((4, 2, 2), (1.0, 0.5, 0.5), 3, kind=ob.SDME_H, dirichlet=inputs.face_bits(0))
+    ud = p.dev(p.mask * p.rand(5, 1e-3))
+    b = p.dev(inputs.uniform(6, p.N, -1, 1))
+    s = p.ctx.jacobi_pcg(p.mat, prec, b, p.zeros(), u_lin=ud, rtol=1e-10, maxit=1, check=False)
+    assert s["status"] == -6 and s["iterations"] == 1
+    assert s["rel_residual"] > 1e-10
+    # the same solve with room to converge
+    s = p.ctx.jacobi_pcg(p.mat, prec, b, p.zeros(), u_lin=ud, rtol=1e-10, check=False)
+    assert s["status"] == 0 and s["rel_residual"] <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_status_breakdown_negative_definite(prec):
+    # K_T + s M with a large negative mass shift is negative definite: the
+    # first p^T A p is negative and CG reports breakdown
+    p = Pair((4, 2, 2), (1.0, 0.5, 0.5), 2, kind=ob.SDME_H, dirichlet=inputs.face_bits(0))
+    ud = p.dev(p.mask * p.rand(7, 1e-3))
+    b = p.dev(inputs.uniform(8, p.N, -1, 1))
+    s = p.ctx.jacobi_pcg(p.mat, prec, b, p.zeros(), u_lin=ud, mass_shift=-1e9, check=False)
+    assert s["status"] == -7
+
+
+def test_binding_refuses_mismatched_device_tensors():
+    # device tensors whose dtype, length or layout does not match the call
+    # are refused by the binding before any launch; the outputs stay as they
+    # were
+    p = Pair((3, 2, 1), (1.0, 0.5, 0.5), 2, kind=ob.SDME_H)
+    torch = p.torch
+    v64 = p.dev(inputs.uniform(9, p.N, -1, 1))
+    y = p.zeros()
+    with pytest.raises(ValueError, match="dtype"):
+        p.ctx.mass_apply(1.0, FP32, v64, y)
+    with pytest.raises(ValueError, match="elements"):
+        p.ctx.mass_apply(1.0, FP64, v64[:-3], y)
+    with pytest.raises(ValueError, match="contiguous"):
+        p.ctx.mass_apply(1.0, FP64, torch.zeros(2 * p.N, dtype=torch.float64,
+                                                device="cuda")[::2], y)
+    with pytest.raises(ValueError, match="elements"):
+        p.ctx.linearize(p.mat, FP64, v64, torch.zeros(p.ctx.nqp * 9, dtype=torch.float64,
+                                                      device="cuda"))
+    short = Pair((3, 2, 1), (1.0, 0.5, 0.5), 2, kind=ob.SDME_H)
+    short.mu_t = short.mu_t[:-1].contiguous()
+    mat = p.ctx.material(short.mu_t, p.lam_t, 1.0)
+    with pytest.raises(ValueError, match="material.mu"):
+        p.ctx.internal_force(mat, FP64, v64, y)
+    assert np.abs(p.host(y)).max() == 0.0
+    # a valid call still runs
+    p.ctx.mass_apply(1.0, FP64, v64, y)
+    assert relerr(p.host(y), p.pb.mesh.mass_apply(1.0, p.host(v64))) < TOL64

@@ -204,3 +204,45 @@ def test_gll_nodal_mass_is_diagonal(P):
     dg = pair.pb.mesh.tangent_diag(0 * pair.pb.mu, 0 * pair.pb.lam, 0 * v, 2.0)
     assert relerr(pair.host(y), dg * v) < TOL64
     assert relerr(ref, dg * v) < TOL64
+
+
+# Basis parameters away from the paper's defaults (Eqs. Y, ParametroK: SD
+# exponent k; Eqs. EffectiveStiffness_lambda, alphaKN: SDME-H weight lambda):
+# the library's tables and every operator built on them against the oracle
+# built with the same parameters.
+PARAM_CASES = [(ob.SDME_M, 0.0, 100.0), (ob.SDME_K, 1.0, 100.0), (ob.SDME_H, 0.5, 1.0),
+               (ob.SDME_H, 0.5, 400.0), (ob.SDME_H, 0.0, 400.0)]
+
+
+@pytest.mark.parametrize("kind,k,lam_h", PARAM_CASES,
+                         ids=["%s-k%g-l%g" % (ob.KIND_NAMES[c[0]], c[1], c[2]) for c in PARAM_CASES])
+def test_operators_with_basis_parameters(kind, k, lam_h):
+    n, P = (9, 2, 1), 4
+    mu, lam = inputs.lognormal_lame(211, n[0] * n[1] * n[2], 1.0e3, 0.3)
+    p = Pair(n, (1.0, 0.75, 1.25), P, kind=kind, dirichlet=inputs.face_bits(0), mu=mu, lam=lam,
+             rho=1.3, k=k, lambda_h=lam_h)
+    u, v = _inputs(p, 12)
+    ud, vd = p.dev(u), p.dev(v)
+    st = p.empty_state()
+    R = p.zeros()
+    p.ctx.internal_force(p.mat, FP64, ud, R, state=st)
+    assert relerr(p.host(R), p.pb.R(u)) < TOL64
+    y = p.zeros()
+    p.ctx.tangent_apply(p.mat, FP64, vd, y, state=st, mass_shift=250.0)
+    ref = p.pb.mesh.tangent_apply(p.pb.mu, p.pb.lam, u, v, 250.0 * p.rho)
+    assert relerr(p.host(y), ref) < TOL64
+    ym = p.zeros()
+    p.ctx.mass_apply(p.rho, FP64, vd, ym)
+    assert relerr(p.host(ym), p.pb.mesh.mass_apply(p.rho, v)) < TOL64
+    d = p.zeros()
+    p.ctx.jacobi_diag(p.mat, FP64, st, 250.0, d)
+    assert relerr(p.host(d), p.pb.mesh.tangent_diag(p.pb.mu, p.pb.lam, u, 250.0 * p.rho)) < TOL64
+    f32 = p.torch.float32
+    u32, v32 = u.astype(np.float32), v.astype(np.float32)
+    st32 = p.empty_state(f32)
+    p.ctx.linearize(p.mat, FP32, p.dev(u32, f32), st32)
+    y32 = p.zeros(f32)
+    p.ctx.tangent_apply(p.mat, FP32, p.dev(v32, f32), y32, state=st32, mass_shift=250.0)
+    ref32 = p.pb.mesh.tangent_apply(p.pb.mu, p.pb.lam, u32.astype(np.float64),
+                                    v32.astype(np.float64), 250.0 * p.rho)
+    assert relerr(p.host(y32), ref32) < TOL32

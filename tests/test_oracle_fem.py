@@ -244,3 +244,53 @@ def test_material_gradient_is_force_sensitivity():
             arr[e] += h
             fd = wv @ (Rp - Rm) / (2 * h)
             assert abs(fd - g[e]) < 1e-7 * max(abs(fd), 1e-3 * np.abs(gm).max())
+
+
+@pytest.mark.parametrize("P,kind", [(1, ob.MODAL), (3, ob.SDME_H), (4, ob.NODAL)])
+def test_strain_energy_vanishes_at_reference_and_under_rotation(P, kind):
+    # Section 3, hyperelastic strain energy: Psi(F = I) = 0 exactly, and the
+    # energy is frame-indifferent, so a rigid rotation stores none either
+    pb, basis = make((2, 2, 1), (1.0, 1.0, 0.5), P, kind=kind)
+    assert pb.mesh.strain_energy(pb.mu, pb.lam, np.zeros(3 * pb.mesh.Nn)) == 0.0
+    th = 0.7
+    Rm = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0, 0, 1.0]])
+    u = osv.affine_field(pb.mesh, basis, (0, 0, 0), (0.2, -0.1, 0.3), Rm - np.eye(3))
+    # scale: energy of a 1% stretch (about 1e-4 mu V)
+    ref = pb.mesh.strain_energy(pb.mu, pb.lam, osv.affine_field(
+        pb.mesh, basis, (0, 0, 0), (0, 0, 0), np.diag([0.01, 0.0, 0.0])))
+    assert abs(pb.mesh.strain_energy(pb.mu, pb.lam, u)) < 1e-10 * ref
+
+
+@pytest.mark.parametrize("s", [0.8, 1.0 + 1e-3, 1.3])
+def test_strain_energy_of_uniaxial_stretch_closed_form(s):
+    # F = diag(s, 1, 1): tr C - 3 = s^2 - 1 and J = s, so the stored energy of
+    # a body of volume V is V [mu/2 (s^2 - 1) - mu ln s + lam/2 (ln s)^2];
+    # per-element Lame parameters enter element by element
+    L = (1.0, 0.5, 0.25)
+    n = (3, 2, 1)
+    pb, basis = make(n, L, 3, kind=ob.SDME_M)
+    rng = np.random.default_rng(5)
+    mu = 300.0 + 200.0 * rng.random(pb.mesh.E)
+    lam = 400.0 + 300.0 * rng.random(pb.mesh.E)
+    u = osv.affine_field(pb.mesh, basis, (0, 0, 0), (0.05, 0.0, -0.02),
+                         np.diag([s - 1.0, 0.0, 0.0]))
+    Ve = np.prod(L) / pb.mesh.E
+    ls = np.log(s)
+    ref = Ve * np.sum(0.5 * mu * (s * s - 1.0) - mu * ls + 0.5 * lam * ls * ls)
+    # tr C - 3 cancels near s = 1: rounding of order eps mu V on top of the
+    # relative bound
+    assert abs(pb.mesh.strain_energy(mu, lam, u) - ref) < 1e-12 * abs(ref) + 1e-13 * Ve * mu.sum()
+
+
+def test_strain_energy_small_strain_limit():
+    # linear-elastic limit of the neo-Hookean energy: for u = t G X,
+    # Pi / t^2 -> V (lam/2 (tr G)^2 + mu |sym G|^2) with an O(t) remainder
+    L = (1.0, 0.75, 0.5)
+    pb, basis = make((2, 1, 1), L, 2)
+    lam0, mu0 = pb.lam[0], pb.mu[0]
+    G = np.array([[0.3, 0.1, -0.2], [0.0, 0.5, 0.4], [0.7, -0.3, 0.2]])
+    eps = 0.5 * (G + G.T)
+    ref = np.prod(L) * (0.5 * lam0 * np.trace(G) ** 2 + mu0 * np.sum(eps * eps))
+    for t, tol in ((1e-3, 5e-3), (1e-4, 5e-4)):
+        u = osv.affine_field(pb.mesh, basis, (0, 0, 0), (0, 0, 0), t * G)
+        assert abs(pb.mesh.strain_energy(pb.mu, pb.lam, u) / t ** 2 - ref) < tol * ref
