@@ -979,15 +979,18 @@ extern "C" int sdme_jacobi_pcg(sdme_ctx *c, const sdme_material *mat, int prec, 
   plan_lin(c, prec, true, bp, w);
   if (!bp.ok) return SDME_ENOMEM;
   if (stats) std::memset(stats, 0, sizeof(*stats));
-  int rc;
+  int rc = SDME_OK;
   if (!mass_only) {
-    if ((rc = clear_flag(c, st))) return rc;
-    if (launch_force<double>(c->P, c->m64, mat->mu, mat->lam, u_lin, nullptr, state64, 0, st))
-      return SDME_EDEVICE;
-    if ((rc = read_flag(c, st))) return rc;
+    if (!(rc = clear_flag(c, st))) {
+      if (launch_force<double>(c->P, c->m64, mat->mu, mat->lam, u_lin, nullptr, state64, 0, st))
+        rc = SDME_EDEVICE;
+      else
+        rc = read_flag(c, st);
+    }
   }
-  rc = solve_linear(c, mat, prec, state64, shift, mass_only != 0, b, x, rtol, maxit, inner_rtol, w,
-                    stats, st);
+  if (!rc)
+    rc = solve_linear(c, mat, prec, state64, shift, mass_only != 0, b, x, rtol, maxit, inner_rtol,
+                      w, stats, st);
   if (hipStreamSynchronize(st) != hipSuccess) rc = SDME_EDEVICE;
   if (stats) {
     stats->status = rc;
