@@ -335,6 +335,26 @@ int sdme_jacobi_pcg(sdme_ctx *ctx, const sdme_material *mat, int prec, const dou
                     void *stream);
 
 /*
+ * sdme_jacobi_pcg_noalloc -- sdme_jacobi_pcg with the workspace taken from a
+ * device-resident scratch array of SDME_NOALLOC_SCRATCH_BYTES bytes inside
+ * the library (one per device, held until the process ends) instead of a
+ * caller buffer: for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * The call allocates nothing; the context must be bound (sdme_bind).
+ * Arguments, results and errors as sdme_jacobi_pcg, plus SDME_ENOMEM when the
+ * solve needs more than SDME_NOALLOC_SCRATCH_BYTES
+ * (sdme_workspace_bytes(ctx, SDME_OP_PCG, prec) tells beforehand; the 32 MiB
+ * hold, at P = 4, about 2.5e5 DOF in FP64 and 1.6e5 DOF in mixed precision).  All calls on one device
+ * share that device's array: calls that overlap in time on one device (from
+ * several host threads or streams) race and must not be made.
+ */
+#define SDME_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sdme_jacobi_pcg_noalloc(sdme_ctx *ctx, const sdme_material *mat, int prec,
+                            const double *u_lin, double mass_shift, int mass_only,
+                            const double *b, double *x, double rtol, int maxit, double inner_rtol,
+                            sdme_stats *stats, void *stream);
+
+/*
  * sdme_newton_static -- Newton-Raphson for R(u) = f_ext (Section 3, the
  * linearised virtual work with the effective stiffness K_T), f_ext nullable
  * (= 0): K_T(u) du = psi = f_ext - R(u) by sdme_jacobi_pcg (inner_rtol 1e-2

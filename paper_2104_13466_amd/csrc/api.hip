@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -379,6 +380,30 @@ size_t lin_bytes(sdme_ctx *c, int prec, bool state32) {
 }  // namespace
 
 
+// Workspace of sdme_jacobi_pcg_noalloc: one array per device, resident for
+// the life of the process.  Host code never uses the array's name as an
+// address: each device's copy is located once with hipGetSymbolAddress (in
+// sdme_bind, or at that entry point's first call on the device) and only that
+// pointer is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SDME_NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of the current device's scratch array (resolved once per device).
+static int scratch_address(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return SDME_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SDME_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SDME_OK;
+}
+
 // Layout of the context's device block (tables, reduction partials, solver
 // scalars) and host block (scalars read back by the drivers); both are
 // allocated by the caller (sdme_context_bytes, sdme_bind).
@@ -558,6 +583,8 @@ extern "C" int sdme_bind(sdme_ctx *c, void *dev_block, size_t dev_bytes, void *h
   c->h_res = (double *)((char *)host_block + 1024);
   c->h_flag = (int *)((char *)host_block + 2048);
   std::memset(host_block, 0, b.host_bytes);
+  void *scr = nullptr;
+  if (scratch_address(&scr)) return SDME_EDEVICE;  // library set-up on this device
   const size_t TS = c->tab_host.size(), TSM = c->tabm_host.size();
   // zero fill by a kernel (no memset node, so a caller may capture the
   // binding), then the tables, both on the caller's stream
@@ -997,6 +1024,24 @@ extern "C" int sdme_jacobi_pcg(sdme_ctx *c, const sdme_material *mat, int prec, 
     stats->time_ms = tm.ms();
   }
   return rc;
+}
+
+
+extern "C" int sdme_jacobi_pcg_noalloc(sdme_ctx *c, const sdme_material *mat, int prec,
+                                       const double *u_lin, double shift, int mass_only,
+                                       const double *b, double *x, double rtol, int maxit,
+                                       double inner_rtol, sdme_stats *stats, void *stream) {
+  if (!c || !valid_prec(prec)) return SDME_EINVAL;
+  if (int rc_ = ensure_device(c)) return rc_;
+  size_t need = 0;
+  if (int rc_ = sdme_workspace_bytes(c, SDME_OP_PCG, prec, &need)) return rc_;
+  if (need > (size_t)SDME_NOALLOC_SCRATCH_BYTES) return SDME_ENOMEM;
+  void *ws = nullptr;
+  if (int rc_ = scratch_address(&ws)) return rc_;
+  // every workspace buffer is written before it is read, so the contents
+  // left by an earlier call need no clearing
+  return sdme_jacobi_pcg(c, mat, prec, u_lin, shift, mass_only, b, x, rtol, maxit, inner_rtol,
+                         stats, ws, (size_t)SDME_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 namespace {

@@ -88,6 +88,8 @@ SIGNATURES = {
     "sdme_workspace_bytes": ([_vp, _i, _i, ctypes.POINTER(_sz)], _i),
     "sdme_jacobi_pcg": ([_vp, ctypes.POINTER(Material), _i, _vp, _d, _i, _vp, _vp, _d, _i, _d,
                          ctypes.POINTER(Stats), _vp, _sz, _vp], _i),
+    "sdme_jacobi_pcg_noalloc": ([_vp, ctypes.POINTER(Material), _i, _vp, _d, _i, _vp, _vp, _d, _i,
+                                 _d, ctypes.POINTER(Stats), _vp], _i),
     "sdme_newton_static": ([_vp, ctypes.POINTER(Material), _i, _vp, _vp, _d, _d, _i, _i,
                             ctypes.POINTER(Stats), _vp, _sz, _vp], _i),
     "sdme_newmark_newton_step": ([_vp, ctypes.POINTER(Material), _i, _vp, _vp, _vp, _vp, _d, _d, _d,
@@ -462,6 +464,19 @@ class Context:
         if check:
             _chk(rc, "jacobi_pcg")
         return st.as_dict()
+
+    def jacobi_pcg_noalloc(self, mat, prec, b, x, u_lin=None, mass_shift=0.0, mass_only=False,
+                           rtol=1e-8, maxit=100000, inner_rtol=1e-2, stream=None, check=True):
+        """sdme_jacobi_pcg with the library's device-resident scratch array
+        as workspace (no allocation per call)."""
+        st = Stats()
+        args = (self._mat(mat), prec, self._v(u_lin, FP64, "u_lin", optional=mass_only),
+                mass_shift, 1 if mass_only else 0, self._v(b, FP64, "b"), self._v(x, FP64, "x"),
+                rtol, maxit, inner_rtol, ctypes.byref(st))
+        rc = self.L.sdme_jacobi_pcg_noalloc(self.handle, *args, self._st(stream))
+        if check:
+            _chk(rc, "jacobi_pcg_noalloc")
+        return rc, st.as_dict()
 
     def newton_static(self, mat, prec, u, f_ext=None, newton_rtol=1e-8, pcg_rtol=1e-8,
                       max_newton=20, max_pcg=100000, stream=None):
