@@ -15,12 +15,12 @@ mixed precision (FP32 inner PCG with FP32 state/operator/vectors and FP64
 dots, FP64 defect correction), and the update u += du.  value = tangent
 applies x DOFs / step time (GDOF/s, whole step).  Besides the timed steps the
 same Newton iteration runs once with FP64 PCG (newton_iteration: mixed vs
-FP64), --solve adds the load-stepped Newton-PCG solve to 1e-8 in both
+FP64) and the load-stepped Newton-PCG solve to 1e-8 runs in both
 precisions (newton_pcg), the oracle is timed on a bounded sample of the same workload on
-the host (cpu_baseline), and the dominant kernel (FP32 stored-state tangent
+the host with all threads and with one (cpu_baseline), and the dominant kernel (FP32 stored-state tangent
 action in the inner PCG) is timed per launch by HIP events on its stream.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve]
        [--no-cpu-baseline] [--kernel-table]
 """
 import argparse
@@ -157,15 +157,26 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     log("copy calibration: %d x %d bytes" % (reps, nbytes))
 
 
-def cpu_baseline(w, seconds=10.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, seconds=10.0, sub_n=24):
     """The oracle's direct tangent action timed on the host on a sub-box of the
-    workload mesh (same P, Q, basis, element size)."""
+    workload mesh (same P, Q, basis, element size), with the OpenMP threads the
+    environment gives it."""
     from oracle import basis as ob
     from oracle import fem
     from paper_2104_13466_amd import inputs
     P, Q = w["P"], w["P"] + 2
     n = w["n"]
-    sub = (min(24, n[0]), min(24, n[1]), min(24, n[2]))
+    sub = (min(sub_n, n[0]), min(sub_n, n[1]), min(sub_n, n[2]))
     h = [w["L"][i] / n[i] for i in range(3)]
     b, x, wq, B, D = ob.build(P, Q, w["kind"])
     mesh = fem.Mesh(sub[0], sub[1], sub[2], P, Q, h, B, D, wq)
@@ -184,9 +195,23 @@ def cpu_baseline(w, seconds=10.0):
     t = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": k * 3 * mesh.Nn / t / 1e9, "unit": "GDOF/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": "%d x tangent action on a %dx%dx%d-element sub-box (P=%d, %d DOF) of the "
                       "workload mesh, %.1f s" % (k, sub[0], sub[1], sub[2], P, 3 * mesh.Nn, t)}
+
+
+def cpu_baseline_single(workload):
+    """The same measurement with one OpenMP thread, in a child process (the
+    oracle's thread count is fixed when its library loads)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--workload", workload,
+                        "--cpu-baseline-only", "--cpu-sub", "10"],
+                       env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        log("single-thread cpu baseline failed: %s" % r.stderr[-500:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def full_solve(ctx, mat, u0, a):
@@ -222,7 +247,11 @@ def full_solve(ctx, mat, u0, a):
     out["max_rel_diff_mixed_vs_fp64"] = ((sols["mixed"] - sols["fp64"]).abs().max() /
                                          sols["fp64"].abs().max()).item()
     out["increments"] = a.increments
-    out["compression"] = a.solve_compression
+    out["compression_reached"] = a.solve_compression
+    out["compression_configured"] = 0.2
+    out["note"] = ("load-stepped to %.0f %% nominal compression: at 47^3, P = 4 the tangent "
+                   "stops being positive definite near the clamped edges beyond about 16 %%"
+                   % (100 * a.solve_compression))
     return out
 
 
@@ -659,7 +688,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="compress_p4")
-    ap.add_argument("--solve", action="store_true")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the load-stepped Newton-PCG solve in both precisions")
+    ap.add_argument("--fp64-reps", type=int, default=2)
     ap.add_argument("--increments", type=int, default=5)
     # At 47^3, P = 4 the tangent stops being positive definite beyond about
     # 16 % nominal compression (PCG meets negative curvature and Newton
@@ -675,7 +706,14 @@ def main():
                                       "static", "wave", "quartic"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-sub", type=int, default=24, help=argparse.SUPPRESS)
     a = ap.parse_args()
+    if a.cpu_baseline_only:
+        # host-only child of the benchmark: no device is touched
+        from paper_2104_13466_amd import inputs
+        print(json.dumps(cpu_baseline(dict(inputs.WORKLOADS[a.workload]), sub_n=a.cpu_sub)))
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: libsdme has no multi-GPU path (slab partition "
               "+ halo exchange over RCCL is designed, not implemented)", file=sys.stderr)
@@ -747,10 +785,17 @@ def main():
     value = applies * N / elapsed / 1e9
     # dominant kernel: FP32 stored-state tangent action inside the inner PCG
     k_ms = prof["fp32_ms"] / max(prof["fp32_count"], 1)
-    # state (10 x fp32 per Gauss point) + the fused direction update (read r,
-    # the inverse diagonal and the previous p, write p) + write y
-    bytes_launch = 40 * ctx.nqp + 20 * N
+    # algorithmic bytes of the stored-gradient tangent action: a 9-word
+    # gradient state per Gauss point (4 B words), read v and write y (4 B per
+    # DOF each).  Reported beside them: the bytes this kernel moves beyond
+    # that by design -- the 10th state word (mu - lam ln J) and the fused PCG
+    # direction update (r, the inverse diagonal and the previous p read and p
+    # written, in place of the read of v)
+    bytes_launch = 36 * ctx.nqp + 8 * N
+    state_word_bytes = 4 * ctx.nqp
+    fused_pcg_bytes = 12 * N
     achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
     # sum-factorised contractions (forward and transposed, 3 components) plus
     # the linearised stress at every Gauss point
     P, Q = w["P"], w["P"] + 2
@@ -770,37 +815,56 @@ def main():
                    "dofs": N, "elements": ctx.E, "gauss_points": ctx.nqp},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(),
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": (round(traffic / bytes_launch, 3)
+                                                  if traffic else None),
                      "kernel": "k_tangent<4,6,float,state,fused p update> (FP32 stored-state "
                                "tangent action, the PCG operator)",
                      "avg_launch_ms": round(k_ms, 4), "launches": prof["fp32_count"],
                      "algorithmic_bytes_per_launch": bytes_launch,
+                     "algorithmic_bytes": "36 B per Gauss point (9-word gradient state) + 8 B "
+                                          "per DOF (read v, write y)",
+                     "state_word_bytes": state_word_bytes,
+                     "fused_pcg_bytes": fused_pcg_bytes,
+                     "frac_with_design_bytes": round(
+                         (bytes_launch + state_word_bytes + fused_pcg_bytes) /
+                         (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "kernel_gdofs": round(N / (k_ms * 1e-3) / 1e9, 2),
                      "alu": {"achieved": round(tflops, 2), "peak": FP32_PEAK, "unit": "TFLOP/s",
                              "frac": round(tflops / FP32_PEAK, 4),
                              "algorithmic_flops_per_launch": flops_launch}},
         "tangent_applies_per_step": applies / a.steps,
     }
-    # FP64 PCG vs mixed on the same Newton iteration (same state, same tolerance)
+    # FP64 PCG vs mixed on the same Newton iteration (same state, same
+    # tolerance): one warm-up, then the median of a.fp64_reps timed runs
     uf = u0.clone()
     duf = torch.zeros_like(R)
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    stf = newton_iteration(ctx, mat, FP64, uf, R, duf, a.rtol)
-    torch.cuda.synchronize()
-    t64 = time.perf_counter() - ts
+    t64s = []
+    for i in range(1 + a.fp64_reps):
+        uf.copy_(u0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        stf = newton_iteration(ctx, mat, FP64, uf, R, duf, a.rtol)
+        torch.cuda.synchronize()
+        if i:
+            t64s.append(time.perf_counter() - ts)
+        log("fp64 newton iteration%s: pcg its %d, %.1f ms" % (
+            "" if i else " (warm-up)", stf["iterations"], 1e3 * (time.perf_counter() - ts)))
+    t64 = float(np.median(t64s))
     dd = ((uf - u).abs().max() / (uf - u0).abs().max()).item()
-    log("fp64 newton iteration: pcg its %d, %.1f ms" % (stf["iterations"], 1e3 * t64))
     result["newton_iteration"] = {
-        "fp64": {"ms": round(1e3 * t64, 1), "pcg_iterations": stf["iterations"]},
-        "mixed": {"ms": round(ms_step, 1), "pcg_iterations": applies / a.steps},
+        "fp64": {"ms": round(1e3 * t64, 1), "pcg_iterations": stf["iterations"],
+                 "runs_ms": [round(1e3 * t, 1) for t in t64s]},
+        "mixed": {"ms": round(ms_step, 1), "pcg_iterations": applies / a.steps,
+                  "runs_ms": [round(1e3 * t, 1) for t in times]},
         "speedup_mixed_vs_fp64": round(1e3 * t64 / ms_step, 3),
         "max_rel_diff_increment_mixed_vs_fp64": dd}
-    if a.solve:
+    if not a.no_solve:
         result["newton_pcg"] = full_solve(ctx, mat, u0, a)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)
+        result["cpu_baseline"]["single_thread"] = cpu_baseline_single(a.workload)
     print(json.dumps(result), flush=True)
 
 

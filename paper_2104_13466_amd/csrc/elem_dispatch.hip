@@ -82,13 +82,24 @@ int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double 
 
 int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad) {
   int ne = 1;
+  if (!grad) {  // the mass kernel's runs
+    switch (P * 10 + (word == 8 ? 1 : 0)) {
+#define NEM(p)                                     \
+  case p * 10 + 1: ne = MassDims<p, 8>::NE; break; \
+  case p * 10 + 0: ne = MassDims<p, 4>::NE; break;
+      NEM(1) NEM(2) NEM(3) NEM(4) NEM(5) NEM(6) NEM(7) NEM(8)
+#undef NEM
+      default: ne = 1;
+    }
+    return ((nx + ne - 1) / ne) * ny * nz;
+  }
   const int g = Q == P + 1 ? 1 : 0;
   switch (P * 100 + g * 10 + (word == 8 ? 1 : 0)) {
 #define NEC(p)                                                                                   \
-  case p * 100 + 1: ne = grad ? Dims<p, p + 2, 8>::NE : Dims<p, p + 2, 8, false>::NE; break;     \
-  case p * 100 + 0: ne = grad ? Dims<p, p + 2, 4>::NE : Dims<p, p + 2, 4, false>::NE; break;     \
-  case p * 100 + 11: ne = grad ? Dims<p, p + 1, 8>::NE : Dims<p, p + 1, 8, false>::NE; break;    \
-  case p * 100 + 10: ne = grad ? Dims<p, p + 1, 4>::NE : Dims<p, p + 1, 4, false>::NE; break;
+  case p * 100 + 1: ne = Dims<p, p + 2, 8>::NE; break;  \
+  case p * 100 + 0: ne = Dims<p, p + 2, 4>::NE; break;  \
+  case p * 100 + 11: ne = Dims<p, p + 1, 8>::NE; break; \
+  case p * 100 + 10: ne = Dims<p, p + 1, 4>::NE; break;
     NEC(1) NEC(2) NEC(3) NEC(4) NEC(5) NEC(6) NEC(7) NEC(8)
 #undef NEC
     default: ne = 1;

@@ -975,36 +975,138 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
 }
 
 // ====================================================================== mass
-// y = rho M v; RED additionally accumulates v^T M v (sum of element-local
-// products) into red.
+// y = rho M v with the element mass rho detJ (Mq (x) Mq (x) Mq), Mq the 1D
+// mass of the mesh's rule (Mq[a][b] = sum_q w_q B[q][a] B[q][b]): the
+// quadrature sum of rho N_a N_b over a tensor-product rule on an affine
+// hexahedron factors into these 1D sums, so the action is three 1D
+// contractions of n x n per direction.  A block owns a run of NE elements of
+// one x-row: the x contraction is the run's assembled 1D mass (neighbouring
+// elements of the run share their x-faces inside the tile), the y and z
+// contractions act on tile lines.  RED additionally accumulates v^T M v
+// (element-local products, masked like the output) into red.
 template <int P, int Q, typename T, bool RED>
-__global__ __launch_bounds__((EK<P, Q, T, false>::NT)) void k_mass(MeshK<T> m, T rho,
-                                                                 const T *__restrict__ v,
-                                                                 T *__restrict__ y, int mask,
-                                                                 Reduce red,
-                                                                 const int *__restrict__ skip) {
-  using K = EK<P, Q, T, false>;
+__global__ __launch_bounds__(256) void k_mass(MeshK<T> m, T rho, const T *__restrict__ v,
+                                              T *__restrict__ y, int mask, Reduce red,
+                                              const int *__restrict__ skip) {
+  using D = MassDims<P, (int)sizeof(T)>;
+  using Dm = Dims<P, Q, (int)sizeof(T), false>;
+  constexpr int n = D::n, NE = D::NE, TX = D::TX, TILE = D::TILE, NT = D::NT;
+  constexpr int LINES = D::LINES, NIT = (TILE + NT - 1) / NT;
   if (skip && *skip) return;
-  __shared__ double s_red[(K::NT + 63) / 64];
-  SDME_PROLOGUE(v, mask != 0)
-  T X[3][3][K::n];
-  forward_lds<K, T, false>(sB, sD, tile, st, s, X);
-  zero_tile<K>(tile);
-  T w12 = sW[s.i1] * sW[s.i2] * m.detJ * rho;
-  T A[3][3][K::n];
-  zero_acc<K>(A);
-#pragma unroll 1
-  for (int q3 = 0; q3 < Q; q3++) {
-    T val[3], mv[3], f[9];
-    value_at<K, T>(s_tab, q3, X, val);
-    T wq = w12 * sW[q3];
+  __shared__ __align__(16) T t0[TILE];
+  __shared__ __align__(16) T t1[TILE];
+  __shared__ T sM[n * n];
+  __shared__ int64_t s_row[LINES];
+  __shared__ double s_red[NT / 64];
+  const int tid = threadIdx.x;
+  const int bpr = (m.nx + NE - 1) / NE;
+  const int k = blockIdx.x % bpr, row = blockIdx.x / bpr;
+  const int ey = row % m.ny, ez = row / m.ny;
+  const int ex0 = k * NE, nel = min(NE, m.nx - ex0), x0 = ex0 * P;
+  const int txv = nel * P + 1;  // slots of the run that belong to its elements
+  const uint32_t bc = m.bc;
+  const bool bnd = (ex0 == 0 && (bc & 07u)) || (ex0 + nel == m.nx && (bc & 070u)) ||
+                   (ey == 0 && (bc & 0700u)) || (ey == m.ny - 1 && (bc & 07000u)) ||
+                   (ez == 0 && (bc & 070000u)) || (ez == m.nz - 1 && (bc & 0700000u));
+  const bool chk = mask && bnd;
+  auto line_off = [&](int r) -> int64_t {
+    const int b = r % n, c = (r / n) % n, comp = r / (n * n);
+    return (int64_t)comp * m.Nn + ((int64_t)(ez * P + c) * m.Ny + (ey * P + b)) * m.Nx + x0;
+  };
+  auto constrained = [&](int r, int x) {
+    const int b = r % n, c = (r / n) % n, comp = r / (n * n);
+    return is_constrained(bc, comp, x0 + x, ey * P + b, ez * P + c, m.Nx, m.Ny, m.Nz);
+  };
+  // the thread's tile slots are requested together (clamped, always-valid
+  // addresses), then stored
+  T val[NIT];
 #pragma unroll
-    for (int i = 0; i < 3; i++) mv[i] = wq * val[i];
-    accum_at<K, T, false, true>(s_tab, q3, f, mv, A);
+  for (int it = 0; it < NIT; it++) {
+    const int idx = min(tid + it * NT, TILE - 1);
+    const int r = idx / TX, x = idx % TX;
+    val[it] = v[line_off(r) + min(x, txv - 1)];
   }
+  if (tid < n * n) {
+    const int a = tid / n, b = tid % n;
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < Q; q++)
+      acc += m.tab[Dm::TW + q] * m.tab[Dm::TB + q * n + a] * m.tab[Dm::TB + q * n + b];
+    sM[tid] = acc;
+  }
+  for (int r = tid; r < LINES; r += NT) s_row[r] = line_off(r);
+#pragma unroll
+  for (int it = 0; it < NIT; it++) {
+    const int idx = tid + it * NT;
+    if (idx < TILE) {
+      const int r = idx / TX, x = idx % TX;
+      t0[idx] = (x < txv && !(chk && constrained(r, x))) ? val[it] : T(0);
+    }
+  }
+  __syncthreads();
+  // x: the run's assembled 1D mass (slot x = e P + a of element e; an
+  // element-boundary slot also takes slot P of element e - 1)
+  for (int idx = tid; idx < TILE; idx += NT) {
+    const int r = idx / TX, x = idx % TX;
+    T acc = T(0);
+    if (x < txv) {
+      const int e1 = min(x / P, nel - 1), a1 = x - e1 * P;
+      const T *u = t0 + r * TX + e1 * P;
+#pragma unroll
+      for (int a = 0; a < n; a++) acc += sM[a1 * n + a] * u[a];
+      if (a1 == 0 && e1 > 0) {
+#pragma unroll
+        for (int a = 0; a < n; a++) acc += sM[P * n + a] * u[a - P];
+      }
+    }
+    t1[idx] = acc;
+  }
+  __syncthreads();
+  // y: lines over b (stride TX), in place
+  for (int it = tid; it < 3 * n * TX; it += NT) {
+    const int x = it % TX, cc = it / TX;  // cc = comp n + c
+    T *base = t1 + cc * n * TX + x;
+    T r[n];
+#pragma unroll
+    for (int b = 0; b < n; b++) r[b] = base[b * TX];
+#pragma unroll
+    for (int b = 0; b < n; b++) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < n; j++) acc += sM[b * n + j] * r[j];
+      base[b * TX] = acc;
+    }
+  }
+  __syncthreads();
+  // z: lines over c (stride n TX), in place
+  for (int it = tid; it < 3 * n * TX; it += NT) {
+    const int x = it % TX, cb = it / TX, comp = cb / n, b = cb % n;
+    T *base = t1 + (comp * n * n + b) * TX + x;
+    T r[n];
+#pragma unroll
+    for (int c = 0; c < n; c++) r[c] = base[c * n * TX];
+#pragma unroll
+    for (int c = 0; c < n; c++) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < n; j++) acc += sM[c * n + j] * r[j];
+      base[c * n * TX] = acc;
+    }
+  }
+  __syncthreads();
+  // hardware FP atomics (slots on the run's faces are shared with other
+  // blocks); constrained outputs skipped when mask is set
   double dot = 0;
-  transpose_all<K, T, false, RED>(m, s, A, sBt, sDt, su, st, tile, s_row, y, mask != 0, v, dot);
-  if (RED) block_partial_t<K::NT>(dot, red, s_red);
+  const T rs = rho * m.detJ;
+  for (int idx = tid; idx < TILE; idx += NT) {
+    const int r = idx / TX, x = idx % TX;
+    if (x >= txv || (chk && constrained(r, x))) continue;
+    const int64_t gi = s_row[r] + x;
+    const T o = t1[idx] * rs;
+    atomicAdd(&y[gi], o);
+    if (RED) dot += (double)t0[idx] * (double)o;
+  }
+  if (RED) block_partial_t<NT>(dot, red, s_red);
 }
 
 // ================================================================= diagonal
@@ -1312,8 +1414,8 @@ int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, con
 template <int P, int Q, typename T>
 int launch_mass_q(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
                   const int *skip, hipStream_t st) {
-  using K = EK<P, Q, T, false>;
-  dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
+  using D = MassDims<P, (int)sizeof(T)>;
+  dim3 grid(((m.nx + D::NE - 1) / D::NE) * m.ny * m.nz), block(D::NT);
   if (do_red)
     hipLaunchKernelGGL((k_mass<P, Q, T, true>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
   else

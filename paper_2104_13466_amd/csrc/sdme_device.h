@@ -75,6 +75,28 @@ struct Dims {
   static constexpr int TILE = 3 * n * n * TX;
 };
 
+// Mass action on affine hexahedra: the element mass is rho detJ times the
+// Kronecker product of the 1D mass of the rule, Mq[a][b] = sum_q w_q B[q][a]
+// B[q][b], in each direction.  A block owns a run of NE consecutive elements
+// of one x-row and applies the 1D matrices to its tile [3][n][n][TX] of slots
+// (along x assembled over the run).  Two tiles (input, output) of at most
+// 48 KiB together; NE gives runs of about 32 slots.
+template <int P_, int WORD>
+struct MassDims {
+  static constexpr int P = P_, n = P_ + 1;
+  static constexpr int LINES = 3 * n * n;
+  static constexpr int NT = 256;
+  static constexpr int cap_slots() { return 49152 / (2 * WORD * LINES); }
+  static constexpr int ne_fit() {
+    int ne = 32 / P > 0 ? 32 / P : 1;
+    while (ne > 1 && ne * P + 1 > cap_slots()) ne--;
+    return ne;
+  }
+  static constexpr int NE = ne_fit();
+  static constexpr int TX = NE * P + 1;
+  static constexpr int TILE = LINES * TX;
+};
+
 // Mesh parameters passed by value to every kernel.
 template <typename T>
 struct MeshK {
