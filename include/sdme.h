@@ -306,6 +306,7 @@ typedef struct {
 #define SDME_OP_NEWMARK 2
 #define SDME_OP_EXPLICIT 3
 #define SDME_OP_ADJOINT 4
+#define SDME_OP_CONDENSED 5
 
 /* Workspace bytes needed by a solver/driver entry point with the given prec
  * (SDME_FP64 or SDME_FP32 = mixed FP32 inner / FP64 outer). */
@@ -333,6 +334,41 @@ int sdme_jacobi_pcg(sdme_ctx *ctx, const sdme_material *mat, int prec, const dou
                     double mass_shift, int mass_only, const double *b, double *x, double rtol,
                     int maxit, double inner_rtol, sdme_stats *stats, void *ws, size_t ws_bytes,
                     void *stream);
+
+/*
+ * Static condensation of the element-interior modes (Section 4, Eqs.
+ * Eq:Matrix_form_schur1, Schur_split1, Schur_split2 and
+ * Eq:Newmark_Matrix_form_schur1; Section 5.2 counts the remaining DOFs).
+ * An interior mode has all three tensor indices internal; it belongs to one
+ * element, so the interior unknowns of A x = b (A = K_T + mass_shift M, or
+ * the mass alone) are eliminated element by element:
+ *   S x_B = g,  S = A_BB - sum_e A_BI inv(A_II) A_IB,  g = b_B - A_BI inv(A_II) b_I,
+ *   x_I = inv(A_II) (b_I - A_IB x_B).
+ *
+ * sdme_condensed_sizes -- host only: out[0] = free DOFs of the condensed
+ * system (not interior, not constrained), out[1] = interior DOFs
+ * (3 E (P-1)^3), out[2] = interior block size per element (3 (P-1)^3).
+ */
+int sdme_condensed_sizes(const sdme_ctx *ctx, int64_t out[3]);
+
+/*
+ * sdme_condensed_pcg -- solve A x = b (as sdme_jacobi_pcg, FP64) through the
+ * condensed system: the interior blocks A_II of every element are formed from
+ * the linearisation at u_lin at the Gauss points and inverted (dense, batched,
+ * workspace E (3 (P-1)^3)^2 doubles), S is applied matrix-free (two operator
+ * actions and one interior solve per iteration) and solved by CG with the
+ * diagonal of A on the remaining DOFs as preconditioner (it omits the Schur
+ * correction of the diagonal), then the interior modes are recovered.  Stops
+ * when ||g - S x_B||_2 <= rtol ||g||_2.  x: dev double [3][Nn], overwritten.
+ * Workspace: sdme_workspace_bytes(ctx, SDME_OP_CONDENSED, SDME_FP64).
+ * Requires the consistent mass (mass_rule 0).  stats->iterations counts the
+ * condensed CG iterations.  Synchronises.  Errors: SDME_EINVAL, SDME_ENOMEM,
+ * SDME_EJAC, SDME_EBREAKDOWN (an interior block or S not positive definite),
+ * SDME_ENOCONV, SDME_EDEVICE.
+ */
+int sdme_condensed_pcg(sdme_ctx *ctx, const sdme_material *mat, const double *u_lin,
+                       double mass_shift, int mass_only, const double *b, double *x, double rtol,
+                       int maxit, sdme_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * sdme_jacobi_pcg_noalloc -- sdme_jacobi_pcg with the workspace taken from a

@@ -151,11 +151,37 @@ struct Op {
   const T *ulin;
   T msr;  // mass_shift * rho
   T rho;
+  // kind 3 (condensed system, FP64): the operator whose interior modes are
+  // condensed (0 tangent, 2 mass), the inverted interior blocks and two
+  // scratch vectors
+  int inner = 0;
+  const double *Kinv = nullptr;
+  double *t = nullptr, *z = nullptr;
 };
 
 template <typename T>
 int apply_op(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *v, T *y, Reduce red,
              int do_red, const int *skip, hipStream_t st, const PUpd<T> *pu = nullptr) {
+  if (op.kind == 3) {
+    // Schur complement of the interior modes applied to v (zero on every
+    // interior slot): t = A v; z = v with z_I = -inv(A_II) t_I (the interior
+    // response, Eq. Schur_split2); y = A z, restricted to the other slots
+    // (Eq. Schur_split1)
+    if constexpr (sizeof(T) == 8) {
+      const int64_t N = 3 * c->Nn;
+      Op<T> in = op;
+      in.kind = op.inner;
+      if (launch_fill<double>(op.t, 0.0, N, st) ||
+          apply_op<T>(c, mat, in, v, op.t, red, 0, skip, st) ||
+          launch_convert<double, double>(op.z, v, 1.0, N, st) ||
+          launch_interior_apply(c->P, c->m64, op.Kinv, op.t, op.z, -1.0, skip, st) ||
+          apply_op<T>(c, mat, in, op.z, y, red, 0, skip, st) ||
+          launch_interior_set(c->P, c->m64, y, 0.0, skip, st))
+        return -1;
+      return 0;
+    }
+    return -2;
+  }
   if (op.kind == 2) return launch_mass<T>(c->P, mkm<T>(c), op.rho, v, y, 1, red, do_red, skip, st);
   if (do_red) return -2;
   return launch_tangent<T>(c->P, mk<T>(c), mat->mu, mat->lam, op.kind == 1 ? op.ulin : nullptr,
@@ -978,6 +1004,11 @@ extern "C" int sdme_workspace_bytes(const sdme_ctx *cc, int op, int prec, size_t
     case SDME_OP_NEWMARK:
       *bytes = st64 + 7 * vec + lin_bytes(c, prec, true);
       break;
+    case SDME_OP_CONDENSED: {
+      const int nI = interior_size(c->P);
+      *bytes = st64 + ((size_t)c->E * nI * nI * sizeof(double) + 255 & ~(size_t)255) + 8 * vec;
+      break;
+    }
     case SDME_OP_EXPLICIT:
     case SDME_OP_ADJOINT:
       *bytes = 6 * vec + 2 * (((size_t)N * sizeof(float) + 255) & ~(size_t)255) +
@@ -1042,6 +1073,106 @@ extern "C" int sdme_jacobi_pcg_noalloc(sdme_ctx *c, const sdme_material *mat, in
   // left by an earlier call need no clearing
   return sdme_jacobi_pcg(c, mat, prec, u_lin, shift, mass_only, b, x, rtol, maxit, inner_rtol,
                          stats, ws, (size_t)SDME_NOALLOC_SCRATCH_BYTES, stream);
+}
+
+extern "C" int sdme_condensed_sizes(const sdme_ctx *c, int64_t out[3]) {
+  if (!c || !out) return SDME_EINVAL;
+  const MeshK<double> &m = c->m64;
+  int64_t fixed = 0;
+  for (int comp = 0; comp < 3; comp++)
+    for (int iz = 0; iz < m.Nz; iz++)
+      for (int iy = 0; iy < m.Ny; iy++)
+        for (int ix = 0; ix < m.Nx; ix++) {
+          uint32_t b = c->d.dirichlet >> comp;
+          if (((b & 1u) && ix == 0) || (((b >> 3) & 1u) && ix == m.Nx - 1) ||
+              (((b >> 6) & 1u) && iy == 0) || (((b >> 9) & 1u) && iy == m.Ny - 1) ||
+              (((b >> 12) & 1u) && iz == 0) || (((b >> 15) & 1u) && iz == m.Nz - 1))
+            fixed++;
+        }
+  const int64_t nI = interior_size(c->P);
+  out[1] = c->E * nI;
+  out[0] = 3 * c->Nn - fixed - out[1];
+  out[2] = nI;
+  return SDME_OK;
+}
+
+extern "C" int sdme_condensed_pcg(sdme_ctx *c, const sdme_material *mat, const double *u_lin,
+                                  double shift, int mass_only, const double *b, double *x,
+                                  double rtol, int maxit, sdme_stats *stats, void *ws,
+                                  size_t ws_bytes, void *stream) {
+  if (!c || !mat || !mat->mu || !mat->lam || !b || !x || (!mass_only && !u_lin) ||
+      !(rtol > 0) || maxit < 1 || c->d.mass_rule != 0 || !std::isfinite(shift))
+    return SDME_EINVAL;
+  if (int rc_ = ensure_device(c)) return rc_;
+  Timer tm;
+  hipStream_t st = S(stream);
+  const int64_t N = 3 * c->Nn;
+  const int P = c->P, nI = interior_size(P);
+  Bump bp(ws, ws_bytes);
+  double *state64 = bp.get<double>(c->nqp * 10);
+  double *Kinv = bp.get<double>((int64_t)c->E * nI * nI);
+  double *bm = bp.get<double>(N), *d = bp.get<double>(N), *r = bp.get<double>(N),
+         *p = bp.get<double>(N), *Ap = bp.get<double>(N), *t = bp.get<double>(N),
+         *z = bp.get<double>(N), *g = bp.get<double>(N);
+  if (!bp.ok) return SDME_ENOMEM;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  int rc = SDME_OK;
+  const double msr = mass_only ? mat->rho : shift * mat->rho;
+  const double *state = mass_only ? nullptr : state64;
+  // linearisation state, interior blocks and their inverses
+  if (!(rc = clear_flag(c, st))) {
+    if (!mass_only &&
+        launch_force<double>(P, c->m64, mat->mu, mat->lam, u_lin, nullptr, state64, 0, st))
+      rc = SDME_EDEVICE;
+    else if (!mass_only)
+      rc = read_flag(c, st);
+  }
+  if (!rc && (launch_interior_block(P, c->m64, mat->mu, mat->lam, state, msr, Kinv, st) ||
+              launch_interior_invert(P, (int)c->E, Kinv, c->flag, st)))
+    rc = SDME_EDEVICE;
+  if (!rc && read_flag(c, st)) rc = SDME_EBREAKDOWN;  // an interior block not SPD
+  // Jacobi preconditioner: the diagonal of the operator on the remaining slots
+  if (!rc && (launch_fill<double>(d, 0.0, N, st) ||
+              launch_diag<double>(P, c->m64, mat->mu, mat->lam, state, msr, d, 1, st) ||
+              launch_bc<double>(d, 1, c->m64, st) ||
+              launch_interior_set(P, c->m64, d, 1.0, nullptr, st) || launch_recip(d, N, st)))
+    rc = SDME_EDEVICE;
+  Op<double> op{3, state, nullptr, mass_only ? 0.0 : msr, mat->rho};
+  op.inner = mass_only ? 2 : 0;
+  op.Kinv = Kinv;
+  op.t = t;
+  op.z = z;
+  Op<double> in = op;
+  in.kind = op.inner;
+  Reduce none{c->partials, c->counter, c->results + 8};
+  // condensed right-hand side g = b - A_{.I} inv(A_II) b_I off the interiors
+  if (!rc && (launch_convert<double, double>(bm, b, 1.0, N, st) ||
+              launch_bc<double>(bm, 0, c->m64, st) || launch_fill<double>(z, 0.0, N, st) ||
+              launch_interior_apply(P, c->m64, Kinv, bm, z, 1.0, nullptr, st) ||
+              launch_fill<double>(t, 0.0, N, st) ||
+              apply_op<double>(c, mat, in, z, t, none, 0, nullptr, st) ||
+              launch_axpbypcz(g, 1.0, bm, 0.0, -1.0, t, N, st) ||
+              launch_interior_set(P, c->m64, g, 0.0, nullptr, st)))
+    rc = SDME_EDEVICE;
+  int its = 0;
+  double rel = 0;
+  if (!rc)
+    rc = pcg_core<double>(c, mat, op, g, x, d, rtol, maxit, r, p, Ap, 0, &its, &rel, st);
+  // interior modes from the boundary solution (Eq. Schur_split2)
+  if ((rc == SDME_OK || rc == SDME_ENOCONV) &&
+      (launch_fill<double>(t, 0.0, N, st) ||
+       apply_op<double>(c, mat, in, x, t, none, 0, nullptr, st) ||
+       launch_axpbypcz(t, 1.0, bm, -1.0, 0.0, t, N, st) ||
+       launch_interior_apply(P, c->m64, Kinv, t, x, 1.0, nullptr, st)))
+    rc = SDME_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) rc = SDME_EDEVICE;
+  if (stats) {
+    stats->iterations = its;
+    stats->rel_residual = rel;
+    stats->status = rc;
+    stats->time_ms = tm.ms();
+  }
+  return rc;
 }
 
 namespace {

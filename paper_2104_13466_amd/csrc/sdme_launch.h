@@ -63,6 +63,21 @@ int launch_face_load(int P, const MeshK<double> &m, int face, const double *t, d
 int launch_l2_error(int P, const MeshK<double> &m, const double *u, const double *g,
                     double *partials, int max_blocks, double *out, hipStream_t st);
 
+// ------------------------------------------------- static condensation (FP64)
+// interior modes per element, 3 (P - 1)^3
+int interior_size(int P);
+// Kii [E][nI][nI] = interior block of K_T + (msr / rho) rho M from the stored state
+int launch_interior_block(int P, const MeshK<double> &m, const double *mu, const double *lam,
+                          const double *state, double msr, double *Kii, hipStream_t st);
+// Kii -> inv(Kii) in place; *flag |= 1 on a non-positive pivot
+int launch_interior_invert(int P, int E, double *Kii, int *flag, hipStream_t st);
+// y_I = scale inv(K_II) t_I on every element's interior slots
+int launch_interior_apply(int P, const MeshK<double> &m, const double *Kinv, const double *t,
+                          double *y, double scale, const int *skip, hipStream_t st);
+// x = val on every interior slot
+int launch_interior_set(int P, const MeshK<double> &m, double *x, double val, const int *skip,
+                        hipStream_t st);
+
 // ------------------------------------------------------------ vector kernels
 // PCG scalars living in device memory (all double).
 struct PcgDev {

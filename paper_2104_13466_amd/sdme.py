@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsdme.so")
 FP64, FP32 = 0, 1
 NODAL, MODAL, SDME_M, SDME_K, SDME_H = 0, 1, 2, 3, 4
 MASK_BC, CHECK_JAC = 1, 2
-OP_PCG, OP_NEWTON, OP_NEWMARK, OP_EXPLICIT, OP_ADJOINT = 0, 1, 2, 3, 4
+OP_PCG, OP_NEWTON, OP_NEWMARK, OP_EXPLICIT, OP_ADJOINT, OP_CONDENSED = 0, 1, 2, 3, 4, 5
 STATUS = {0: "SDME_OK", -1: "SDME_EINVAL", -2: "SDME_ENOMEM", -3: "SDME_EDEVICE", -4: "SDME_EEIG",
           -5: "SDME_EJAC", -6: "SDME_ENOCONV", -7: "SDME_EBREAKDOWN", -8: "SDME_ENAN"}
 
@@ -90,6 +90,9 @@ SIGNATURES = {
                          ctypes.POINTER(Stats), _vp, _sz, _vp], _i),
     "sdme_jacobi_pcg_noalloc": ([_vp, ctypes.POINTER(Material), _i, _vp, _d, _i, _vp, _vp, _d, _i,
                                  _d, ctypes.POINTER(Stats), _vp], _i),
+    "sdme_condensed_sizes": ([_vp, ctypes.POINTER(_i64)], _i),
+    "sdme_condensed_pcg": ([_vp, ctypes.POINTER(Material), _vp, _d, _i, _vp, _vp, _d, _i,
+                            ctypes.POINTER(Stats), _vp, _sz, _vp], _i),
     "sdme_newton_static": ([_vp, ctypes.POINTER(Material), _i, _vp, _vp, _d, _d, _i, _i,
                             ctypes.POINTER(Stats), _vp, _sz, _vp], _i),
     "sdme_newmark_newton_step": ([_vp, ctypes.POINTER(Material), _i, _vp, _vp, _vp, _vp, _d, _d, _d,
@@ -477,6 +480,27 @@ class Context:
         if check:
             _chk(rc, "jacobi_pcg_noalloc")
         return rc, st.as_dict()
+
+    def condensed_sizes(self):
+        """(free DOFs of the condensed system, interior DOFs, interior block
+        size per element) -- host only."""
+        out = (ctypes.c_int64 * 3)()
+        _chk(self.L.sdme_condensed_sizes(self.handle, out), "condensed_sizes")
+        return tuple(int(v) for v in out)
+
+    def condensed_pcg(self, mat, b, x, u_lin=None, mass_shift=0.0, mass_only=False, rtol=1e-8,
+                      maxit=100000, stream=None, check=True):
+        """FP64 solve of (K_T + s M) x = b (or M x = b) by static condensation
+        of the element-interior modes (sdme_condensed_pcg)."""
+        st = Stats()
+        args = (self._mat(mat), self._v(u_lin, FP64, "u_lin", optional=mass_only), mass_shift,
+                1 if mass_only else 0, self._v(b, FP64, "b"), self._v(x, FP64, "x"), rtol, maxit,
+                ctypes.byref(st))
+        ws, nb = self._wsargs(OP_CONDENSED, FP64)
+        rc = self.L.sdme_condensed_pcg(self.handle, *args, ws, nb, self._st(stream))
+        if check:
+            _chk(rc, "condensed_pcg")
+        return st.as_dict()
 
     def newton_static(self, mat, prec, u, f_ext=None, newton_rtol=1e-8, pcg_rtol=1e-8,
                       max_newton=20, max_pcg=100000, stream=None):
