@@ -682,6 +682,75 @@ def case_quartic(a):
             "time_error_ratios_per_halving": [round(x, 3) for x in rates]}
 
 
+def case_condense(a):
+    """Static condensation of the element-interior modes (sdme_condensed_pcg)
+    against the full Jacobi-PCG on the same FP64 systems, both to 1e-8:
+    the Newmark matrix b1 M + K_T (b1 = 4 / dt^2, dt = 0.1) of the 16x4x4
+    cantilever (P = 4) at a seeded state for SDME-H, SDME-M and the nodal basis;
+    its explicit mass solve (SDME-M); and the tangent of the 47^3, P = 4
+    compression workload at its initial guess with right-hand side -R."""
+    import torch
+
+    from paper_2104_13466_amd import inputs
+    from paper_2104_13466_amd.sdme import FP64, MASK_BC, Context
+
+    def compare(ctx, mat, b, ulin, shift, mass_only, reps):
+        out = {}
+        xs = {}
+        for name in ("full", "condensed"):
+            x = torch.zeros_like(b)
+            ts = []
+            for r in range(1 + reps):
+                x.zero_()
+                if name == "full":
+                    st, ms = timed(lambda: ctx.jacobi_pcg(mat, FP64, b, x, u_lin=ulin,
+                                                          mass_shift=shift, mass_only=mass_only,
+                                                          rtol=1e-8))
+                else:
+                    st, ms = timed(lambda: ctx.condensed_pcg(mat, b, x, u_lin=ulin,
+                                                             mass_shift=shift,
+                                                             mass_only=mass_only, rtol=1e-8))
+                if r:
+                    ts.append(ms)
+            out[name] = {"iterations": st["iterations"], "ms": round(float(np.median(ts)), 2)}
+            xs[name] = x
+        out["speedup_condensed"] = round(out["full"]["ms"] / out["condensed"]["ms"], 3)
+        out["max_rel_diff"] = ((xs["full"] - xs["condensed"]).abs().max() /
+                               xs["full"].abs().max()).item()
+        return out
+
+    rows = []
+    w = inputs.WORKLOADS["cantilever_p4"]
+    lam0, mu0 = inputs.lame(w["E"], w["nu"])
+    for kind, mass_only in ((4, False), (2, False), (0, False), (2, True)):
+        ctx = Context(w["n"], w["L"], w["P"], basis=kind, dirichlet=w["dirichlet"])
+        mu = torch.full((ctx.E,), mu0, dtype=torch.float64, device="cuda")
+        lam = torch.full((ctx.E,), lam0, dtype=torch.float64, device="cuda")
+        mat = Context.material(mu, lam, w["rho"])
+        free = 1.0 - ctx.dirichlet_flags().astype(np.float64)
+        u = torch.tensor(free * inputs.random_coeffs(w["seed"], w["n"], w["P"], 1e-3),
+                         device="cuda")
+        b = torch.tensor(free * inputs.uniform(w["seed"], 3 * ctx.Nn, -1, 1, stream=5),
+                         device="cuda")
+        r = compare(ctx, mat, b, u, 4.0 / 0.1 ** 2, mass_only, 3)
+        r.update(workload="cantilever_p4", basis=KIND_NAMES[kind],
+                 system="rho M" if mass_only else "b1 M + K_T, b1 = 400",
+                 condensed_dofs=ctx.condensed_sizes()[0], full_free_dofs=int(free.sum()))
+        log("condense %s" % r)
+        rows.append(r)
+        ctx.close()
+    wl, ctx, mat, u0 = setup("compress_p4")
+    R = torch.zeros_like(u0)
+    ctx.internal_force(mat, FP64, u0, R, flags=MASK_BC)
+    ctx.axpby(-1.0, R, 0.0, R)
+    r = compare(ctx, mat, R, u0, 0.0, False, 1)
+    r.update(workload="compress_p4", basis="sdme_h", system="K_T at the initial guess, b = -R",
+             condensed_dofs=ctx.condensed_sizes()[0])
+    log("condense %s" % r)
+    rows.append(r)
+    return {"case": "condense", "tolerance": 1e-8, "precision": "fp64", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -703,7 +772,7 @@ def main():
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params",
-                                      "static", "wave", "quartic"],
+                                      "static", "wave", "quartic", "condense"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -725,7 +794,7 @@ def main():
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
               "adjoint": case_adjoint, "params": case_params, "static": case_static,
-              "wave": case_wave, "quartic": case_quartic}[a.case]
+              "wave": case_wave, "quartic": case_quartic, "condense": case_condense}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)
