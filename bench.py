@@ -73,7 +73,7 @@ def measured_traffic():
         return None
 
 
-def setup(name, kind=None, k=0.5, lambda_h=100.0):
+def setup(name, kind=None, k=0.5, lambda_h=100.0, ordered=False):
     import torch
 
     from paper_2104_13466_amd import inputs
@@ -82,7 +82,8 @@ def setup(name, kind=None, k=0.5, lambda_h=100.0):
     if kind is not None:
         w["kind"] = kind
     n, L, P = w["n"], w["L"], w["P"]
-    ctx = Context(n, L, P, basis=w["kind"], k=k, lambda_h=lambda_h, dirichlet=w["dirichlet"])
+    ctx = Context(n, L, P, basis=w["kind"], k=k, lambda_h=lambda_h, dirichlet=w["dirichlet"],
+                  ordered=ordered)
     lam0, mu0 = inputs.lame(w["E"], w["nu"])
     dev = torch.device("cuda")
     mu = torch.full((ctx.E,), mu0, dtype=torch.float64, device=dev)
@@ -751,6 +752,39 @@ def case_condense(a):
     return {"case": "condense", "tolerance": 1e-8, "precision": "fp64", "rows": rows}
 
 
+def case_ordered(a):
+    """Ordered assembly against hardware atomics on the workload: per-launch
+    times of the element operators (kernel plus gather), and one Newton
+    iteration (PCG to 1e-8, FP64 and mixed) run twice from the same state:
+    iteration counts and whether the two solutions agree bit for bit."""
+    import torch
+
+    from paper_2104_13466_amd.sdme import FP32, FP64
+    out = {"case": "ordered", "workload": a.workload, "modes": {}}
+    for ordered in (False, True):
+        w, ctx, mat, u0 = setup(a.workload, ordered=ordered)
+        rows = kernel_table(ctx, mat, u0)
+        mode = {"kernels_ms": {"%s_%s" % (r[0], r[1]): round(r[2], 4) for r in rows},
+                "device_block_bytes": ctx.context_bytes()[0]}
+        for prec in (FP64, FP32):
+            runs = []
+            for _ in range(2):
+                u = u0.clone()
+                R, du = torch.zeros_like(u), torch.zeros_like(u)
+                st, ms = timed(lambda: newton_iteration(ctx, mat, prec, u, R, du, 1e-8))
+                runs.append((st, ms, u))
+            key = "fp64" if prec == FP64 else "mixed"
+            mode["newton_" + key] = {
+                "iterations": [r[0]["iterations"] for r in runs],
+                "ms": [round(r[1], 1) for r in runs],
+                "bitwise_equal": bool(torch.equal(runs[0][2], runs[1][2])),
+                "max_abs_diff": (runs[0][2] - runs[1][2]).abs().max().item()}
+            log("ordered=%s %s %s" % (ordered, key, mode["newton_" + key]))
+        out["modes"]["ordered" if ordered else "atomic"] = mode
+        ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -772,7 +806,7 @@ def main():
                          "copy (for counter runs)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--case", choices=["sweep", "newmark", "explicit", "adjoint", "params",
-                                      "static", "wave", "quartic", "condense"],
+                                      "static", "wave", "quartic", "condense", "ordered"],
                     help="print the JSON line of a further measurement instead of the benchmark")
     ap.add_argument("--steps-explicit", type=int, default=2000)
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
@@ -794,7 +828,8 @@ def main():
     if a.case:
         fn = {"sweep": case_sweep, "newmark": case_newmark, "explicit": case_explicit,
               "adjoint": case_adjoint, "params": case_params, "static": case_static,
-              "wave": case_wave, "quartic": case_quartic, "condense": case_condense}[a.case]
+              "wave": case_wave, "quartic": case_quartic, "condense": case_condense,
+              "ordered": case_ordered}[a.case]
         print(json.dumps(fn(a)), flush=True)
         return
     log("setup %s" % a.workload)

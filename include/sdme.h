@@ -119,7 +119,18 @@ typedef struct {
                       /* sdme_mass_apply, mass solves, explicit steps, energies */
                       /* and sdme_lambda_max; the mass-shifted operators        */
                       /* (mass_shift != 0, Newmark) then return SDME_EINVAL     */
+  int assembly;       /* SDME_ASSEMBLY_ATOMIC: element contributions to shared  */
+                      /* slots are added with hardware atomics (the order of    */
+                      /* the additions, and so the last bits of the sums, may   */
+                      /* differ between runs); SDME_ASSEMBLY_ORDERED: they are  */
+                      /* staged and added in ascending element order (the       */
+                      /* assembly over elements of Section 2), so every result, */
+                      /* PCG and Newton iterates included, repeats bit for bit; */
+                      /* the device block then also holds the staging array     */
 } sdme_mesh_desc;
+
+#define SDME_ASSEMBLY_ATOMIC 0
+#define SDME_ASSEMBLY_ORDERED 1
 
 /* Create a context for a structured box mesh (host only).  The basis is
  * built on the host (sdme_basis_build) at once; its tables are uploaded to
@@ -133,7 +144,9 @@ int sdme_destroy(sdme_ctx *ctx);
 
 /* Sizes of the memory a context needs from the caller: *dev_bytes of device
  * memory (basis tables of the volume and mass rules in FP64 and FP32, the
- * Jacobian flag, PCG scalars, per-block reduction partials) and *host_bytes
+ * Jacobian flag, PCG scalars, per-block reduction partials and, with
+ * SDME_ASSEMBLY_ORDERED, the staging array: the larger of the element
+ * kernels' output tiles and 3 (P+1)^3 words per element, in FP64) and *host_bytes
  * of host memory (solver scalars copied back by the drivers).  Host-only.
  * Errors: SDME_EINVAL. */
 int sdme_context_bytes(const sdme_ctx *ctx, size_t *dev_bytes, size_t *host_bytes);

@@ -12,7 +12,7 @@ OUT = os.path.join(HERE, "libsdme.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HIP_SOURCES = ["elem_dispatch.hip", "vec_kernels.hip", "load_kernels.hip", "condense_kernels.hip",
-               "api.hip"]
+               "assemble_kernels.hip", "api.hip"]
 # element kernels: one translation unit per polynomial order
 ORDERS = range(1, 9)
 HOST_SOURCES = ["basis.cpp"]

@@ -24,7 +24,7 @@ using namespace sdme;
 // Offsets of the parts of the context's device block, and its size.
 struct BlockPlan {
   size_t o_tm64 = 0, o_tm32 = 0, o_t64 = 0, o_t32 = 0, o_flag = 0, o_pcg = 0, o_part = 0,
-         o_cnt = 0, o_res = 0, dev_bytes = 0, host_bytes = 0;
+         o_cnt = 0, o_res = 0, o_stage = 0, stage_bytes = 0, dev_bytes = 0, host_bytes = 0;
 };
 // Host block: PcgDev[2] at 0, double[16] at 1024, int at 2048.
 constexpr size_t HOST_BLOCK_BYTES = 4096;
@@ -461,6 +461,22 @@ static void plan_blocks(sdme_ctx *c) {
   b.o_part = take(sizeof(double) * 2 * (size_t)nblk);
   b.o_cnt = take(sizeof(unsigned) * 4);
   b.o_res = take(sizeof(double) * 16);
+  // ordered assembly: staging for the largest output of an element launch
+  // (element kernels' tiles, element vectors of the diagonal and the body
+  // load; face-element vectors are smaller), in either precision
+  b.stage_bytes = 0;
+  if (d->assembly == SDME_ASSEMBLY_ORDERED) {
+    const size_t n3 = (size_t)c->n * c->n * c->n;
+    for (int word : {4, 8}) {
+      size_t w = (size_t)c->E * 3 * n3;
+      for (int q : {c->Q, c->mm64.Q})
+        for (bool grad : {true, false})
+          w = std::max(w, (size_t)elem_blocks(P, q, word, d->nx, d->ny, d->nz, grad) *
+                              (size_t)elem_tile_words(P, q, word, grad));
+      b.stage_bytes = std::max(b.stage_bytes, w * word);
+    }
+  }
+  b.o_stage = take(b.stage_bytes);
   b.dev_bytes = bytes;
   b.host_bytes = HOST_BLOCK_BYTES;
   c->tab32_host.resize(TS);
@@ -526,6 +542,7 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->P < 1 || d->P > 8 ||
       (d->Q != d->P + 2 && d->Q != d->P + 1) || d->mass_rule < 0 || d->mass_rule > 1 ||
       d->basis < 0 || d->basis > 4 || !(d->k >= 0 && d->k <= 1) || !(d->lambda_h >= 0) ||
+      (d->assembly != SDME_ASSEMBLY_ATOMIC && d->assembly != SDME_ASSEMBLY_ORDERED) ||
       !(d->h[0] > 0 && d->h[1] > 0 && d->h[2] > 0) || (d->dirichlet >> 18) != 0)
     return SDME_EINVAL;
   int64_t Nx = (int64_t)d->nx * d->P + 1, Ny = (int64_t)d->ny * d->P + 1,
@@ -562,6 +579,7 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   m.detJ = d->h[0] * d->h[1] * d->h[2] / 8.0;
   m.tab = nullptr;
   m.flag = nullptr;
+  m.stage = nullptr;
   MeshK<float> &f = c->m32;
   f.nx = m.nx; f.ny = m.ny; f.nz = m.nz; f.E = m.E;
   f.Nx = m.Nx; f.Ny = m.Ny; f.Nz = m.Nz; f.Nn = m.Nn; f.Q = m.Q;
@@ -570,6 +588,7 @@ extern "C" int sdme_create(const sdme_mesh_desc *d, sdme_ctx **out) {
   f.detJ = (float)m.detJ;
   f.tab = nullptr;
   f.flag = nullptr;
+  f.stage = nullptr;
   c->mm64 = c->m64;
   c->mm32 = c->m32;
   if (!c->tabm_host.empty()) c->mm64.Q = c->mm32.Q = c->P + 1;
@@ -613,8 +632,9 @@ extern "C" int sdme_bind(sdme_ctx *c, void *dev_block, size_t dev_bytes, void *h
   if (scratch_address(&scr)) return SDME_EDEVICE;  // library set-up on this device
   const size_t TS = c->tab_host.size(), TSM = c->tabm_host.size();
   // zero fill by a kernel (no memset node, so a caller may capture the
-  // binding), then the tables, both on the caller's stream
-  if (launch_fill<double>((double *)dev_block, 0.0, (int64_t)(b.dev_bytes / 8), st) ||
+  // binding; the staging array is written before it is read and is left as
+  // it is), then the tables, both on the caller's stream
+  if (launch_fill<double>((double *)dev_block, 0.0, (int64_t)(b.o_stage / 8), st) ||
       hipMemcpyAsync(c->tab64, c->tab_host.data(), sizeof(double) * TS, hipMemcpyHostToDevice,
                      st) != hipSuccess ||
       hipMemcpyAsync(c->tab32, c->tab32_host.data(), sizeof(float) * TS, hipMemcpyHostToDevice,
@@ -633,6 +653,11 @@ extern "C" int sdme_bind(sdme_ctx *c, void *dev_block, size_t dev_bytes, void *h
   c->mm64.flag = c->mm32.flag = c->flag;
   c->mm64.tab = TSM ? c->tabm64 : c->tab64;
   c->mm32.tab = TSM ? c->tabm32 : c->tab32;
+  // one staging array for both precisions: its users run one after another
+  // on the call's stream
+  double *stage64 = b.stage_bytes ? (double *)(base + b.o_stage) : nullptr;
+  c->m64.stage = c->mm64.stage = stage64;
+  c->m32.stage = c->mm32.stage = (float *)stage64;
   c->dev_ready = true;
   return SDME_OK;
 }

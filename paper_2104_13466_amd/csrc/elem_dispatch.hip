@@ -80,32 +80,49 @@ int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double 
 #undef C
 }
 
-int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad) {
-  int ne = 1;
-  if (!grad) {  // the mass kernel's runs
+namespace {
+struct TileShape {
+  int ne, tx, tile;
+};
+template <class D>
+TileShape shape_of() {
+  return {D::NE, D::TX, D::TILE};
+}
+// Elements per block, tile slots along x and tile words of an element kernel
+// launch (grad = false: the mass kernel's runs).
+TileShape tile_shape(int P, int Q, int word, bool grad) {
+  if (!grad) {
     switch (P * 10 + (word == 8 ? 1 : 0)) {
-#define NEM(p)                                     \
-  case p * 10 + 1: ne = MassDims<p, 8>::NE; break; \
-  case p * 10 + 0: ne = MassDims<p, 4>::NE; break;
+#define NEM(p)                                               \
+  case p * 10 + 1: return shape_of<MassDims<p, 8>>(); \
+  case p * 10 + 0: return shape_of<MassDims<p, 4>>();
       NEM(1) NEM(2) NEM(3) NEM(4) NEM(5) NEM(6) NEM(7) NEM(8)
 #undef NEM
-      default: ne = 1;
+      default: return {1, P + 1, 3 * (P + 1) * (P + 1) * (P + 1)};
     }
-    return ((nx + ne - 1) / ne) * ny * nz;
   }
   const int g = Q == P + 1 ? 1 : 0;
   switch (P * 100 + g * 10 + (word == 8 ? 1 : 0)) {
-#define NEC(p)                                                                                   \
-  case p * 100 + 1: ne = Dims<p, p + 2, 8>::NE; break;  \
-  case p * 100 + 0: ne = Dims<p, p + 2, 4>::NE; break;  \
-  case p * 100 + 11: ne = Dims<p, p + 1, 8>::NE; break; \
-  case p * 100 + 10: ne = Dims<p, p + 1, 4>::NE; break;
+#define NEC(p)                                                 \
+  case p * 100 + 1: return shape_of<Dims<p, p + 2, 8>>();  \
+  case p * 100 + 0: return shape_of<Dims<p, p + 2, 4>>();  \
+  case p * 100 + 11: return shape_of<Dims<p, p + 1, 8>>(); \
+  case p * 100 + 10: return shape_of<Dims<p, p + 1, 4>>();
     NEC(1) NEC(2) NEC(3) NEC(4) NEC(5) NEC(6) NEC(7) NEC(8)
 #undef NEC
-    default: ne = 1;
+    default: return {1, P + 1, 3 * (P + 1) * (P + 1) * (P + 1)};
   }
+}
+}  // namespace
+
+int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad) {
+  const int ne = tile_shape(P, Q, word, grad).ne;
   return ((nx + ne - 1) / ne) * ny * nz;
 }
+int elem_tile_words(int P, int Q, int word, bool grad) {
+  return tile_shape(P, Q, word, grad).tile;
+}
+int elem_run(int P, int Q, int word, bool grad) { return tile_shape(P, Q, word, grad).ne; }
 
 template int launch_force<double>(int, const MeshK<double> &, const double *, const double *,
                                   const double *, double *, double *, int, hipStream_t);

@@ -640,6 +640,16 @@ __device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s,
                                                const T *__restrict__ vdot, double &dot) {
   const int xe = m.Nx - s.x0;
   const bool chk = mask && s.bnd;
+  if (m.stage) {
+    // deterministic assembly: the tile is staged, a gather kernel adds it
+    T *__restrict__ out = m.stage + (size_t)blockIdx.x * K::TILE;
+    tile_for<K>([&](int idx, int r, int x) {
+      out[idx] = tile[idx];
+      if (RED && !(x >= xe || (chk && tile_constrained<K>(m, s, r, x))))
+        dot += (double)vdot[s_row[r] + x] * (double)tile[idx];
+    });
+    return;
+  }
   tile_for<K>([&](int idx, int r, int x) {
     if (x >= xe || (chk && tile_constrained<K>(m, s, r, x))) return;
     const int64_t gi = s_row[r] + x;
@@ -1098,12 +1108,13 @@ __global__ __launch_bounds__(256) void k_mass(MeshK<T> m, T rho, const T *__rest
   // blocks); constrained outputs skipped when mask is set
   double dot = 0;
   const T rs = rho * m.detJ;
+  T *__restrict__ staged = m.stage ? m.stage + (size_t)blockIdx.x * TILE : nullptr;
   for (int idx = tid; idx < TILE; idx += NT) {
     const int r = idx / TX, x = idx % TX;
-    if (x >= txv || (chk && constrained(r, x))) continue;
-    const int64_t gi = s_row[r] + x;
     const T o = t1[idx] * rs;
-    atomicAdd(&y[gi], o);
+    if (staged) staged[idx] = o;  // deterministic assembly: gathered afterwards
+    if (x >= txv || (chk && constrained(r, x))) continue;
+    if (!staged) atomicAdd(&y[s_row[r] + x], o);
     if (RED) dot += (double)t0[idx] * (double)o;
   }
   if (RED) block_partial_t<NT>(dot, red, s_red);
@@ -1242,7 +1253,9 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_diag(MeshK<T> m, const do
                  sBD[q * n + s.i1] * sg[(2 * n + c) * n * Q + s.i2 * Q + q];
         if (s.valid) {
           int ix = s.ex * P + s.i1, iy = s.ey * P + s.i2, iz = s.ez * P + c;
-          if (!(mask && is_constrained(m.bc, i, ix, iy, iz, m.Nx, m.Ny, m.Nz)))
+          if (m.stage)  // deterministic assembly: element vector, gathered afterwards
+            m.stage[((size_t)s.e * 3 + i) * K::n3 + (c * n + s.i2) * n + s.i1] = val;
+          else if (!(mask && is_constrained(m.bc, i, ix, iy, iz, m.Nx, m.Ny, m.Nz)))
             atomicAdd(&d[(size_t)i * m.Nn + ((size_t)iz * m.Ny + iy) * m.Nx + ix], val);
         }
       }
@@ -1371,6 +1384,8 @@ int launch_force_q(const MeshK<T> &m, const double *mu, const double *lam, const
     hipLaunchKernelGGL((k_force<P, Q, T, false, true>), grid, block, 0, st, m, mu, lam, u, R, state, mask);
   else
     hipLaunchKernelGGL((k_force<P, Q, T, true, false>), grid, block, 0, st, m, mu, lam, u, R, state, mask);
+  if (R && m.stage && launch_stage_gather<T>(P, m, K::NE, K::TX, K::TILE, mask, R, nullptr, st))
+    return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template <int P, typename T>
@@ -1401,6 +1416,7 @@ int launch_tangent_q(const MeshK<T> &m, const double *mu, const double *lam, con
     if (mass) SDME_TAN(false, true, false); else SDME_TAN(false, false, false);
   }
 #undef SDME_TAN
+  if (m.stage && launch_stage_gather<T>(P, m, K::NE, K::TX, K::TILE, mask, y, skip, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template <int P, typename T>
@@ -1420,6 +1436,7 @@ int launch_mass_q(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce r
     hipLaunchKernelGGL((k_mass<P, Q, T, true>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
   else
     hipLaunchKernelGGL((k_mass<P, Q, T, false>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
+  if (m.stage && launch_stage_gather<T>(P, m, D::NE, D::TX, D::TILE, mask, y, skip, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template <int P, typename T>
@@ -1436,6 +1453,7 @@ int launch_diag_q(const MeshK<T> &m, const double *mu, const double *lam, const 
   static_assert(3 * K::n * K::n * Q <= K::SE, "diag LDS layout");
   dim3 grid(blocks_for<K>(m.nx, m.ny, m.nz)), block(K::NT);
   hipLaunchKernelGGL((k_diag<P, Q, T>), grid, block, 0, st, m, mu, lam, state, msr, d, mask);
+  if (m.stage && launch_stage_gather_elem<T>(P, m, mask, d, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template <int P, typename T>

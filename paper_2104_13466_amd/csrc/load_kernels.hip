@@ -62,7 +62,10 @@ __global__ __launch_bounds__(NTL) void k_body_load(MeshK<double> m, const double
     const int a = i % n, b = (i / n) % n, cc = (i / (n * n)) % n, c = i / (n * n * n);
     double acc = 0;
     for (int q3 = 0; q3 < Q; q3++) acc += sB[q3 * n + cc] * s0[((c * Q + q3) * n + b) * n + a];
-    atomicAdd(&f[(size_t)c * m.Nn + grid_slot(m, P, ex, ey, ez, a, b, cc)], acc);
+    if (m.stage)  // ordered assembly: element vector, gathered afterwards
+      m.stage[((size_t)e * 3 + c) * (n * n * n) + (cc * n + b) * n + a] = acc;
+    else
+      atomicAdd(&f[(size_t)c * m.Nn + grid_slot(m, P, ex, ey, ez, a, b, cc)], acc);
   }
 }
 
@@ -115,8 +118,13 @@ __global__ __launch_bounds__(128) void k_face_load(MeshK<double> m, int face,
     li[g.t2] = b;
     li[g.dir] = g.side ? P : 0;
     const size_t s = grid_slot(m, P, g.ei[0], g.ei[1], g.ei[2], li[0], li[1], li[2]);
+    if (m.stage) {  // ordered assembly: face-element vector, gathered afterwards
 #pragma unroll
-    for (int c = 0; c < 3; c++) atomicAdd(&f[(size_t)c * m.Nn + s], acc[c]);
+      for (int c = 0; c < 3; c++) m.stage[((size_t)fe * 3 + c) * n * n + idx] = acc[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; c++) atomicAdd(&f[(size_t)c * m.Nn + s], acc[c]);
+    }
   }
 }
 
@@ -205,6 +213,7 @@ int launch_body_load(int P, const MeshK<double> &m, const double *b, double *f, 
     break;
   SDME_PSWITCH(BL)
 #undef BL
+  if (m.stage && launch_stage_gather_elem<double>(P, m, 0, f, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -217,6 +226,7 @@ int launch_face_load(int P, const MeshK<double> &m, int face, const double *t, d
     break;
   SDME_PSWITCH(FL)
 #undef FL
+  if (m.stage && launch_stage_gather_face(P, m, face, f, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -108,6 +108,10 @@ struct MeshK {
   T detJ;        // h_x h_y h_z / 8
   const T *tab;  // device basis tables (layout of Dims)
   int *flag;     // device status word: set to 1 when det F <= 0
+  // deterministic assembly: element kernels store their blocks' output tiles
+  // (or element vectors) here and a gather kernel sums every slot's
+  // contributions in a fixed order; nullptr: hardware atomics
+  T *stage;
 };
 
 // Deterministic block reduction target: each block writes a partial, the last

@@ -42,6 +42,21 @@ int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double 
 // Blocks of an element kernel launch with Q points per direction (grad =
 // false: the value-only mass kernel).
 int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad = true);
+// Words of one block's output tile (the staging stride of the deterministic
+// assembly) and the elements per block.
+int elem_tile_words(int P, int Q, int word, bool grad = true);
+int elem_run(int P, int Q, int word, bool grad = true);
+// Deterministic assembly: y[slot] = sum of the staged tiles holding the slot
+// (runs of ne elements, tiles of tx slots along x, stride tile words), in
+// ascending block order; constrained slots get 0 with mask.
+template <typename T>
+int launch_stage_gather(int P, const MeshK<T> &m, int ne, int tx, int tile, int mask, T *y,
+                        const int *skip, hipStream_t st);
+// The same over element vectors [E][3][(P+1)^3] (the Jacobi diagonal).
+template <typename T>
+int launch_stage_gather_elem(int P, const MeshK<T> &m, int mask, T *y, hipStream_t st);
+// The same over face-element vectors [fe][3][(P+1)^2] of one boundary face.
+int launch_stage_gather_face(int P, const MeshK<double> &m, int face, double *f, hipStream_t st);
 
 // ------------------------------------------------------------- face kernels
 // mode 0: traction f += scale * int N t dA on face `face`

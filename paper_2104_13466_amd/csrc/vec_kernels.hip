@@ -419,8 +419,13 @@ __global__ __launch_bounds__(128) void k_face(MeshK<double> m, int mode, int fac
     li[t1d] = a; li[t2d] = b; li[dir] = local_d;
     int gi[3] = {ei[0] * P + li[0], ei[1] * P + li[1], ei[2] * P + li[2]};
     size_t g = ((size_t)gi[2] * Nd[1] + gi[1]) * Nd[0] + gi[0];
-    for (int c = (mode == 0 ? 0 : 2); c < 3; c++)
-      if (acc[c] != 0.0) atomicAdd(&f[c * (size_t)m.Nn + g], scale * acc[c]);
+    if (m.stage) {  // ordered assembly: face-element vector, gathered afterwards
+      for (int c = 0; c < 3; c++)
+        m.stage[((size_t)fe * 3 + c) * n * n + midx] = c >= (mode == 0 ? 0 : 2) ? scale * acc[c] : 0.0;
+    } else {
+      for (int c = (mode == 0 ? 0 : 2); c < 3; c++)
+        if (acc[c] != 0.0) atomicAdd(&f[c * (size_t)m.Nn + g], scale * acc[c]);
+    }
   }
   if (do_red) {
     // block energy -> partial; last block sums (deterministic)
@@ -467,6 +472,7 @@ int launch_face(int P, const MeshK<double> &m, int mode, int face, const double 
     default: return -2;
   }
 #undef FC
+  if (f && m.stage && launch_stage_gather_face(P, m, face, f, st)) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -34,7 +34,8 @@ class MeshDesc(ctypes.Structure):
                 ("P", ctypes.c_int), ("Q", ctypes.c_int), ("basis", ctypes.c_int),
                 ("k", ctypes.c_double), ("lambda_h", ctypes.c_double),
                 ("h", ctypes.c_double * 3), ("origin", ctypes.c_double * 3),
-                ("dirichlet", ctypes.c_uint32), ("mass_rule", ctypes.c_int)]
+                ("dirichlet", ctypes.c_uint32), ("mass_rule", ctypes.c_int),
+                ("assembly", ctypes.c_int)]
 
 
 class Material(ctypes.Structure):
@@ -209,7 +210,7 @@ class Context:
     """Structured box mesh + basis (sdme_create / sdme_destroy)."""
 
     def __init__(self, n, L, P, basis=SDME_H, k=0.5, lambda_h=100.0, dirichlet=0, origin=(0, 0, 0),
-                 Q=None, lumped_mass=False):
+                 Q=None, lumped_mass=False, ordered=False):
         self.L = _lib()
         self.P, self.Q = P, (P + 2 if Q is None else Q)
         d = MeshDesc()
@@ -221,6 +222,9 @@ class Context:
             d.origin[i] = origin[i]
         d.dirichlet = dirichlet
         d.mass_rule = 1 if lumped_mass else 0
+        # ordered assembly: staged element outputs summed in element order
+        # (bitwise repeatable) instead of hardware atomics
+        d.assembly = 1 if ordered else 0
         self.desc = d
         self.n = tuple(n)
         self.h = [d.h[i] for i in range(3)]

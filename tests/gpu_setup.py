@@ -16,12 +16,13 @@ def relerr(a, b):
 
 class Pair:
     def __init__(self, n, L, P, kind=4, dirichlet=0, mu=None, lam=None, rho=1.0, E=1.0e3, nu=0.3,
-                 Q=None, k=0.5, lambda_h=100.0):
+                 Q=None, k=0.5, lambda_h=100.0, ordered=False):
         import torch
         self.torch = torch
         self.pb, self.basis = make(n, L, P, Q=Q, kind=kind, dirichlet=dirichlet, mu=mu, lam=lam,
                                    rho=rho, E=E, nu=nu, k=k, lam_h=lambda_h)
-        self.ctx = Context(n, L, P, basis=kind, dirichlet=dirichlet, Q=Q, k=k, lambda_h=lambda_h)
+        self.ctx = Context(n, L, P, basis=kind, dirichlet=dirichlet, Q=Q, k=k, lambda_h=lambda_h,
+                           ordered=ordered)
         self.n, self.P, self.rho = n, P, rho
         self.mu_t = self.dev(self.pb.mu)
         self.lam_t = self.dev(self.pb.lam)

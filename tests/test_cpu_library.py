@@ -107,6 +107,26 @@ def test_argument_validation():
         sdme.Context((2, 2, 2), (1, 1, 1), 3, Q=3)
 
 
+@pytest.mark.parametrize("n,P,Q", [((41, 2, 3), 1, None), ((9, 2, 2), 5, 6), ((3, 1, 2), 8, None)])
+def test_ordered_assembly_adds_staging_to_the_device_block(n, P, Q):
+    # ordered assembly: the device block also holds the staging array, at
+    # least one FP64 element vector per element (the diagonal and body load)
+    plain = sdme.Context(n, (1.0, 1.0, 1.0), P, Q=Q)
+    ordered = sdme.Context(n, (1.0, 1.0, 1.0), P, Q=Q, ordered=True)
+    assert ordered.desc.assembly == 1 and plain.desc.assembly == 0
+    extra = ordered.context_bytes()[0] - plain.context_bytes()[0]
+    assert extra % 256 == 0 and extra >= 8 * 3 * plain.E * (P + 1) ** 3
+    assert ordered.context_bytes()[1] == plain.context_bytes()[1]
+    # any other assembly mode is refused
+    import ctypes
+    d = sdme.MeshDesc.from_buffer_copy(plain.desc)
+    d.assembly = 2
+    h = ctypes.c_void_p()
+    assert plain.L.sdme_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    plain.close()
+    ordered.close()
+
+
 def test_context_accepts_gll_rule():
     # Q = P+1 selects the Gauss-Lobatto-Legendre volume rule (host-only query)
     c = sdme.Context((2, 1, 1), (1.0, 1.0, 1.0), 3, basis=ob.NODAL, Q=4)
