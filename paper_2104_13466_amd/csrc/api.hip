@@ -838,15 +838,12 @@ extern "C" int sdme_mass_apply(sdme_ctx *c, double rho, int prec, const void *v,
   if (!c || !v || !y || !valid_prec(prec) || !std::isfinite(rho)) return SDME_EINVAL;
   if (int rc_ = ensure_device(c)) return rc_;
   hipStream_t st = S(stream);
-  int64_t N = 3 * c->Nn;
   int mask = (flags & SDME_MASK_BC) ? 1 : 0;
   Reduce none{c->partials, c->counter, c->results + 8};
-  if (prec == SDME_FP64) {
-    if (launch_fill<double>((double *)y, 0.0, N, st)) return SDME_EDEVICE;
+  // the mass kernel writes every slot of y (no zero fill first)
+  if (prec == SDME_FP64)
     return lerr(launch_mass<double>(c->P, c->mm64, rho, (const double *)v, (double *)y, mask, none,
                                     0, nullptr, st));
-  }
-  if (launch_fill<float>((float *)y, 0.0f, N, st)) return SDME_EDEVICE;
   return lerr(launch_mass<float>(c->P, c->mm32, (float)rho, (const float *)v, (float *)y, mask,
                                  none, 0, nullptr, st));
 }
@@ -1466,8 +1463,7 @@ extern "C" int sdme_energies(sdme_ctx *c, const sdme_material *mat, const double
   if (launch_axpbypcz(w.t1, 0.5 / dt, u_next, 0.0, -0.5 / dt, u_prev, N, st) ||
       launch_fill<double>(w.t2, 0.0, N, st) ||
       launch_mass<double>(c->P, c->mm64, mat->rho, w.t1, w.t2, 0, red_at(c, 12), 1, nullptr, st) ||
-      launch_fin2(red_at(c, 12),
-                  elem_blocks(c->P, c->mm64.Q, 8, c->d.nx, c->d.ny, c->d.nz, false), st))
+      launch_fin2(red_at(c, 12), mass_blocks<double>(c->P, c->mm64), st))
     return SDME_EDEVICE;
   if (hipMemcpyAsync(c->h_res, c->results + 12, sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||

@@ -16,6 +16,8 @@ int launch_tangent_t(const MeshK<T> &, const double *, const double *, const T *
 template <int P, typename T>
 int launch_mass_t(const MeshK<T> &, T, const T *, T *, int, Reduce, int, const int *, hipStream_t);
 template <int P, typename T>
+int mass_blocks_t(const MeshK<T> &);
+template <int P, typename T>
 int launch_diag_t(const MeshK<T> &, const double *, const double *, const T *, T, T *, int,
                   hipStream_t);
 template <int P>
@@ -67,6 +69,15 @@ int launch_diag(int P, const MeshK<T> &m, const double *mu, const double *lam, c
   SDME_DISPATCH(P, C)
 #undef C
 }
+template <typename T>
+int mass_blocks(int P, const MeshK<T> &m) {
+#define C(p) mass_blocks_t<p, T>(m)
+  SDME_DISPATCH(P, C)
+#undef C
+}
+template int mass_blocks<double>(int, const MeshK<double> &);
+template int mass_blocks<float>(int, const MeshK<float> &);
+
 int launch_energy(int P, const MeshK<double> &m, const double *mu, const double *lam,
                   const double *u, Reduce red, hipStream_t st) {
 #define C(p) launch_energy_t<p>(m, mu, lam, u, red, st)
@@ -89,18 +100,8 @@ TileShape shape_of() {
   return {D::NE, D::TX, D::TILE};
 }
 // Elements per block, tile slots along x and tile words of an element kernel
-// launch (grad = false: the mass kernel's runs).
-TileShape tile_shape(int P, int Q, int word, bool grad) {
-  if (!grad) {
-    switch (P * 10 + (word == 8 ? 1 : 0)) {
-#define NEM(p)                                               \
-  case p * 10 + 1: return shape_of<MassDims<p, 8>>(); \
-  case p * 10 + 0: return shape_of<MassDims<p, 4>>();
-      NEM(1) NEM(2) NEM(3) NEM(4) NEM(5) NEM(6) NEM(7) NEM(8)
-#undef NEM
-      default: return {1, P + 1, 3 * (P + 1) * (P + 1) * (P + 1)};
-    }
-  }
+// launch with a gradient (the mass kernel has no tile).
+TileShape tile_shape(int P, int Q, int word) {
   const int g = Q == P + 1 ? 1 : 0;
   switch (P * 100 + g * 10 + (word == 8 ? 1 : 0)) {
 #define NEC(p)                                                 \
@@ -113,16 +114,27 @@ TileShape tile_shape(int P, int Q, int word, bool grad) {
     default: return {1, P + 1, 3 * (P + 1) * (P + 1) * (P + 1)};
   }
 }
+// Upper bound of the mass kernel's blocks (one z chunk per element).
+int mass_blocks_max(int P, int word, int nx, int ny, int nz) {
+  switch (P * 10 + (word == 8 ? 1 : 0)) {
+#define NEM(p)                                                                         \
+  case p * 10 + 1: return kron_grid<KronDims<p, 8>>(nx, ny, nz, 1 << 30).blocks(); \
+  case p * 10 + 0: return kron_grid<KronDims<p, 4>>(nx, ny, nz, 1 << 30).blocks();
+    NEM(1) NEM(2) NEM(3) NEM(4) NEM(5) NEM(6) NEM(7) NEM(8)
+#undef NEM
+    default: return 1;
+  }
+}
 }  // namespace
 
 int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad) {
-  const int ne = tile_shape(P, Q, word, grad).ne;
+  if (!grad) return mass_blocks_max(P, word, nx, ny, nz);
+  const int ne = tile_shape(P, Q, word).ne;
   return ((nx + ne - 1) / ne) * ny * nz;
 }
 int elem_tile_words(int P, int Q, int word, bool grad) {
-  return tile_shape(P, Q, word, grad).tile;
+  return grad ? tile_shape(P, Q, word).tile : 0;
 }
-int elem_run(int P, int Q, int word, bool grad) { return tile_shape(P, Q, word, grad).ne; }
 
 template int launch_force<double>(int, const MeshK<double> &, const double *, const double *,
                                   const double *, double *, double *, int, hipStream_t);

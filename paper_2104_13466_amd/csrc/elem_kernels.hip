@@ -985,137 +985,287 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
 }
 
 // ====================================================================== mass
-// y = rho M v with the element mass rho detJ (Mq (x) Mq (x) Mq), Mq the 1D
-// mass of the mesh's rule (Mq[a][b] = sum_q w_q B[q][a] B[q][b]): the
-// quadrature sum of rho N_a N_b over a tensor-product rule on an affine
-// hexahedron factors into these 1D sums, so the action is three 1D
-// contractions of n x n per direction.  A block owns a run of NE elements of
-// one x-row: the x contraction is the run's assembled 1D mass (neighbouring
-// elements of the run share their x-faces inside the tile), the y and z
-// contractions act on tile lines.  RED additionally accumulates v^T M v
-// (element-local products, masked like the output) into red.
-template <int P, int Q, typename T, bool RED>
-__global__ __launch_bounds__(256) void k_mass(MeshK<T> m, T rho, const T *__restrict__ v,
-                                              T *__restrict__ y, int mask, Reduce red,
-                                              const int *__restrict__ skip) {
-  using D = MassDims<P, (int)sizeof(T)>;
-  using Dm = Dims<P, Q, (int)sizeof(T), false>;
-  constexpr int n = D::n, NE = D::NE, TX = D::TX, TILE = D::TILE, NT = D::NT;
-  constexpr int LINES = D::LINES, NIT = (TILE + NT - 1) / NT;
+// y = rho M v on affine hexahedra with one density: the element mass is
+// rho detJ (Mq (x) Mq (x) Mq) with Mq[a][b] = sum_q w_q B[q][a] B[q][b] the 1D
+// mass of the mesh's rule (the quadrature sum of rho N_a N_b over a
+// tensor-product rule factors into these 1D sums), so the assembled mass is
+// rho detJ times the Kronecker product of the assembled 1D masses: slot
+// e P + l (0 <= l < P) of a direction takes sum_a Mq[l][a] v(e P + a) from
+// element e and, at l = 0, also sum_a Mq[P][a] v((e - 1) P + a) from element
+// e - 1.  A block owns the output box of KronDims and marches along z through
+// its input planes: each plane is loaded once (x and y halos P, zero outside
+// the mesh and, with mask, on constrained slots), filtered along x and y in
+// LDS, and accumulated per z element in registers; every output slot is
+// stored once (constrained ones as zero with mask).  RED also sums v . y over
+// the block's unconstrained outputs into the block partial (v^T M v).
+#ifndef SDME_KRON_XCD
+#define SDME_KRON_XCD 1
+#endif
+template <int P, typename T, bool RED>
+__global__ __launch_bounds__((KronDims<P, (int)sizeof(T)>::NT)) void k_mass(
+    MeshK<T> m, T rs, const T *__restrict__ v, T *__restrict__ y, int mask, Reduce red,
+    const int *__restrict__ skip, KronGrid g) {
+  using D = KronDims<P, (int)sizeof(T)>;
+  constexpr int n = D::n, NT = D::NT, EX = D::EX, TX = D::TX, RY = D::RY, GPE = D::GPE,
+                IX = D::IX, IY = D::IY, IXP = D::IXP, TXP = D::TXP, NLD = D::NLD;
+  constexpr int NXI = (EX * IY + NT - 1) / NT;  // x-pass items per thread
+  // the 1D mass in registers where it is small, else read from LDS
+  constexpr bool MQR = n * n * (int)sizeof(T) <= 100;
   if (skip && *skip) return;
-  __shared__ __align__(16) T t0[TILE];
-  __shared__ __align__(16) T t1[TILE];
+  // input and x-filtered planes, two of each (plane z uses buffer z & 1)
+  __shared__ __align__(16) T sIn[2][IY * IXP];
+  __shared__ __align__(16) T sX[2][IY * TXP];
   __shared__ T sM[n * n];
-  __shared__ int64_t s_row[LINES];
   __shared__ double s_red[NT / 64];
-  const int tid = threadIdx.x;
-  const int bpr = (m.nx + NE - 1) / NE;
-  const int k = blockIdx.x % bpr, row = blockIdx.x / bpr;
-  const int ey = row % m.ny, ez = row / m.ny;
-  const int ex0 = k * NE, nel = min(NE, m.nx - ex0), x0 = ex0 * P;
-  const int txv = nel * P + 1;  // slots of the run that belong to its elements
-  const uint32_t bc = m.bc;
-  const bool bnd = (ex0 == 0 && (bc & 07u)) || (ex0 + nel == m.nx && (bc & 070u)) ||
-                   (ey == 0 && (bc & 0700u)) || (ey == m.ny - 1 && (bc & 07000u)) ||
-                   (ez == 0 && (bc & 070000u)) || (ez == m.nz - 1 && (bc & 0700000u));
-  const bool chk = mask && bnd;
-  auto line_off = [&](int r) -> int64_t {
-    const int b = r % n, c = (r / n) % n, comp = r / (n * n);
-    return (int64_t)comp * m.Nn + ((int64_t)(ez * P + c) * m.Ny + (ey * P + b)) * m.Nx + x0;
-  };
-  auto constrained = [&](int r, int x) {
-    const int b = r % n, c = (r / n) % n, comp = r / (n * n);
-    return is_constrained(bc, comp, x0 + x, ey * P + b, ez * P + c, m.Nx, m.Ny, m.Nz);
-  };
-  // the thread's tile slots are requested together (clamped, always-valid
-  // addresses), then stored
-  T val[NIT];
-#pragma unroll
-  for (int it = 0; it < NIT; it++) {
-    const int idx = min(tid + it * NT, TILE - 1);
-    const int r = idx / TX, x = idx % TX;
-    val[it] = v[line_off(r) + min(x, txv - 1)];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int b = blockIdx.x;
+#if SDME_KRON_XCD
+  {  // blocks b, b + 8, ... run on one XCD: give each XCD a contiguous range
+    const int G = g.blocks(), per = G / 8, rem = G % 8, xcd = b % 8, k = b / 8;
+    b = xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
   }
+#endif
+  const int xt = b % g.nxt;
+  b /= g.nxt;
+  const int yt = b % g.nyt;
+  b /= g.nyt;
+  const int zc = b % g.nzc, comp = b / g.nzc;
+  const int ex0 = xt * D::EX, ey0 = yt * D::EY, ez_lo = zc * g.cz,
+            ez_hi = min(m.nz, ez_lo + g.cz);
+  const int x0 = ex0 * P, y0 = ey0 * P, Nx = m.Nx, Ny = m.Ny, Nz = m.Nz;
+  const uint32_t mb = mask ? (m.bc >> comp) : 0u;
   if (tid < n * n) {
-    const int a = tid / n, b = tid % n;
+    const int Q = m.Q, a = tid / n, c = tid % n;
+    const T *B = m.tab, *W = m.tab + 2 * Q * n;
     T acc = T(0);
-#pragma unroll
-    for (int q = 0; q < Q; q++)
-      acc += m.tab[Dm::TW + q] * m.tab[Dm::TB + q * n + a] * m.tab[Dm::TB + q * n + b];
+    for (int q = 0; q < Q; q++) acc += W[q] * B[q * n + a] * B[q * n + c];
     sM[tid] = acc;
   }
-  for (int r = tid; r < LINES; r += NT) s_row[r] = line_off(r);
+  // the thread's input-plane slots: in-plane offset (-1: outside the mesh or
+  // constrained on an x or y face with mask) and LDS position (-1: none)
+  int off[NLD], lpos[NLD];
 #pragma unroll
-  for (int it = 0; it < NIT; it++) {
-    const int idx = tid + it * NT;
-    if (idx < TILE) {
-      const int r = idx / TX, x = idx % TX;
-      t0[idx] = (x < txv && !(chk && constrained(r, x))) ? val[it] : T(0);
-    }
+  for (int i = 0; i < NLD; i++) {
+    const int idx = tid + i * NT, r = idx / IX, c = idx - r * IX;
+    const int gx = x0 - P + c, gy = y0 - P + r;
+    const bool ok = idx < IX * IY && gx >= 0 && gx < Nx && gy >= 0 && gy < Ny &&
+                    !((mb & 1u) && gx == 0) && !((mb & 8u) && gx == Nx - 1) &&
+                    !((mb & 64u) && gy == 0) && !((mb & 512u) && gy == Ny - 1);
+    off[i] = ok ? gy * Nx + gx : -1;
+    lpos[i] = idx < IX * IY ? r * IXP + c : -1;
   }
-  __syncthreads();
-  // x: the run's assembled 1D mass (slot x = e P + a of element e; an
-  // element-boundary slot also takes slot P of element e - 1)
-  for (int idx = tid; idx < TILE; idx += NT) {
-    const int r = idx / TX, x = idx % TX;
-    T acc = T(0);
-    if (x < txv) {
-      const int e1 = min(x / P, nel - 1), a1 = x - e1 * P;
-      const T *u = t0 + r * TX + e1 * P;
+  // the thread's x-pass items (element je of the tile, row r): LDS offsets
+  // of its input row segment and output, and what the element contributes
+  // (bit 0: its own term, element < nx; bit 1: the vertex's element-(e - 1)
+  // term, e > 0; none past the element index nx, which only owns the vertex)
+  int xin[NXI], xout[NXI], xfl[NXI];
 #pragma unroll
-      for (int a = 0; a < n; a++) acc += sM[a1 * n + a] * u[a];
-      if (a1 == 0 && e1 > 0) {
+  for (int k = 0; k < NXI; k++) {
+    // consecutive lanes take consecutive elements of a row (contiguous LDS
+    // segments)
+    const int it = tid + k * NT, r = it / EX, je = it - r * EX, e = ex0 + je;
+    const bool act = it < EX * IY && e <= m.nx;
+    xin[k] = r * IXP + je * P;
+    xout[k] = r * TXP + je * P;
+    xfl[k] = act ? ((e < m.nx ? 1 : 0) | (e > 0 ? 2 : 0)) : 0;
+  }
+  const T *vp = v + (size_t)comp * m.Nn;
+  const size_t plane_sz = (size_t)Nx * Ny;
+  T pre[NLD];
+  auto request = [&](int z) {
+    const bool zok = !((mb & 4096u) && z == 0) && !((mb & 32768u) && z == Nz - 1);
+    const T *pz = vp + (size_t)z * plane_sz;
 #pragma unroll
-        for (int a = 0; a < n; a++) acc += sM[P * n + a] * u[a - P];
+    for (int i = 0; i < NLD; i++) pre[i] = (zok && off[i] >= 0) ? pz[off[i]] : T(0);
+  };
+  auto commit = [&](T *dst) {
+#pragma unroll
+    for (int i = 0; i < NLD; i++)
+      if (lpos[i] >= 0) dst[lpos[i]] = pre[i];
+  };
+  __syncthreads();  // sM
+  T mq[MQR ? n * n : 1];
+  if constexpr (MQR) {
+#pragma unroll
+    for (int i = 0; i < n * n; i++) mq[i] = sM[i];
+  }
+  auto M = [&](int l, int a) -> T {
+    if constexpr (MQR)
+      return mq[l * n + a];
+    else
+      return sM[l * n + a];
+  };
+  // x pass: the P slots of the item's element in its row (in[0..P]: element
+  // e - 1, in[P..2P]: element e)
+  auto xpass = [&](const T *src, T *dst) {
+#pragma unroll
+    for (int k = 0; k < NXI; k++) {
+      const int fl = xfl[k];
+      if (!fl) continue;
+      const T *in = src + xin[k];
+      T u[2 * P + 1];  // slots of element e - 1 (0 .. P) and e (P .. 2P)
+      if constexpr (D::VEC) {
+        constexpr int VW = D::VW;
+        using V = T __attribute__((ext_vector_type(VW)));
+#pragma unroll
+        for (int q = 0; q < 2 * P / VW; q++) {
+          const V t = *reinterpret_cast<const V *>(in + q * VW);
+#pragma unroll
+          for (int c = 0; c < VW; c++) u[q * VW + c] = t[c];
+        }
+        u[2 * P] = in[2 * P];
+      } else {
+#pragma unroll
+        for (int a = 0; a <= 2 * P; a++) u[a] = in[a];
+      }
+      T o[P];
+#pragma unroll
+      for (int l = 0; l < P; l++) o[l] = T(0);
+      if (fl & 1) {
+#pragma unroll
+        for (int a = 0; a < n; a++) {
+#pragma unroll
+          for (int l = 0; l < P; l++) o[l] += M(l, a) * u[P + a];
+        }
+      }
+      if (fl & 2) {
+#pragma unroll
+        for (int a = 0; a < n; a++) o[0] += M(P, a) * u[a];
+      }
+      T *out = dst + xout[k];
+      if constexpr (D::VEC) {
+        // past the element index nx only slot 0 is written
+        constexpr int VW = D::VW;
+        using V = T __attribute__((ext_vector_type(VW)));
+        if (fl & 1) {
+#pragma unroll
+          for (int q = 0; q < P / VW; q++) {
+            V t;
+#pragma unroll
+            for (int c = 0; c < VW; c++) t[c] = o[q * VW + c];
+            *reinterpret_cast<V *>(out + q * VW) = t;
+          }
+        } else {
+          out[0] = o[0];
+        }
+      } else {
+        out[0] = o[0];
+        if (fl & 1) {
+#pragma unroll
+          for (int l = 1; l < P; l++) out[l] = o[l];
+        }
       }
     }
-    t1[idx] = acc;
-  }
-  __syncthreads();
-  // y: lines over b (stride TX), in place
-  for (int it = tid; it < 3 * n * TX; it += NT) {
-    const int x = it % TX, cc = it / TX;  // cc = comp n + c
-    T *base = t1 + cc * n * TX + x;
-    T r[n];
+  };
+  // y pass: wave wv owns rows l0 .. l0 + RY - 1 of element ey, lane = x slot
+  const int gq = wv / GPE, ey = ey0 + gq, l0 = (wv % GPE) * RY;
+  const int gx = x0 + lane;
+  const int xcl = min(lane, TX - 1);
+  const bool xok = lane < TX && gx < Nx;
+  auto ypass = [&](const T *src, T (&w)[RY]) {
+    const T *col = src + (gq * P) * TXP + xcl;  // rows of element ey - 1, then ey
 #pragma unroll
-    for (int b = 0; b < n; b++) r[b] = base[b * TX];
+    for (int j = 0; j < RY; j++) w[j] = T(0);
+    if (ey < m.ny) {
 #pragma unroll
-    for (int b = 0; b < n; b++) {
-      T acc = T(0);
+      for (int a = 0; a < n; a++) {
+        const T u = col[(P + a) * TXP];
 #pragma unroll
-      for (int j = 0; j < n; j++) acc += sM[b * n + j] * r[j];
-      base[b * TX] = acc;
+        for (int j = 0; j < RY; j++) w[j] += M(l0 + j, a) * u;
+      }
     }
-  }
-  __syncthreads();
-  // z: lines over c (stride n TX), in place
-  for (int it = tid; it < 3 * n * TX; it += NT) {
-    const int x = it % TX, cb = it / TX, comp = cb / n, b = cb % n;
-    T *base = t1 + (comp * n * n + b) * TX + x;
-    T r[n];
+    if (l0 == 0 && ey > 0 && ey <= m.ny) {
 #pragma unroll
-    for (int c = 0; c < n; c++) r[c] = base[c * n * TX];
-#pragma unroll
-    for (int c = 0; c < n; c++) {
-      T acc = T(0);
-#pragma unroll
-      for (int j = 0; j < n; j++) acc += sM[c * n + j] * r[j];
-      base[c * n * TX] = acc;
+      for (int a = 0; a < n; a++) w[0] += M(P, a) * col[a * TXP];
     }
-  }
-  __syncthreads();
-  // hardware FP atomics (slots on the run's faces are shared with other
-  // blocks); constrained outputs skipped when mask is set
+  };
   double dot = 0;
-  const T rs = rho * m.detJ;
-  T *__restrict__ staged = m.stage ? m.stage + (size_t)blockIdx.x * TILE : nullptr;
-  for (int idx = tid; idx < TILE; idx += NT) {
-    const int r = idx / TX, x = idx % TX;
-    const T o = t1[idx] * rs;
-    if (staged) staged[idx] = o;  // deterministic assembly: gathered afterwards
-    if (x >= txv || (chk && constrained(r, x))) continue;
-    if (!staged) atomicAdd(&y[s_row[r] + x], o);
-    if (RED) dot += (double)t0[idx] * (double)o;
+  // the thread's output rows: in-plane offset (-1: no output) and whether
+  // the slot is constrained on an x or y face (with mask)
+  int orow[RY];
+  unsigned ocon = 0;
+#pragma unroll
+  for (int j = 0; j < RY; j++) {
+    const int gy = y0 + gq * P + l0 + j;
+    const bool ok = xok && gy < Ny && ey <= m.ny;
+    orow[j] = ok ? gy * Nx + gx : -1;
+    if (((mb & 1u) && gx == 0) || ((mb & 8u) && gx == Nx - 1) || ((mb & 64u) && gy == 0) ||
+        ((mb & 512u) && gy == Ny - 1))
+      ocon |= 1u << j;
+  }
+  T *yc = y + (size_t)comp * m.Nn;
+  // outputs of row j of this wave at plane zo (val = accumulated sum)
+  auto emit = [&](int zo, int j, T val) {
+    if (orow[j] < 0) return;
+    const bool con = ((ocon >> j) & 1u) || ((mb & 4096u) && zo == 0) ||
+                     ((mb & 32768u) && zo == Nz - 1);
+    const size_t gi = (size_t)zo * plane_sz + orow[j];
+    const T o = con ? T(0) : val * rs;
+    yc[gi] = o;
+    if (RED && !con) dot += (double)vp[gi] * (double)o;
+  };
+  // z march over the planes z0 .. zlast of elements e_start .. ez_hi - 1
+  // (e_start = ez_lo - 1 supplies the contribution of element ez_lo - 1 to
+  // the chunk's first vertex plane).  Plane z = e P + a adds Mq[l][a] w to
+  // the accumulators of element e; at a vertex plane element e - 1 is
+  // complete: its planes are stored and the vertex starts element e.
+  // One barrier per plane: plane z + 1 is stored to the other LDS buffer
+  // before it, plane z + 2 requested after it.
+  const int e_start = ez_lo > 0 ? ez_lo - 1 : 0, z0 = e_start * P, zlast = ez_hi * P;
+  T w[RY], acc[RY][n], carry[RY];
+#pragma unroll
+  for (int j = 0; j < RY; j++) {
+    carry[j] = T(0);
+#pragma unroll
+    for (int l = 0; l < n; l++) acc[j][l] = T(0);
+  }
+  request(z0);
+  commit(sIn[0]);
+  if (z0 + 1 <= zlast) request(z0 + 1);
+  __syncthreads();
+  for (int z = z0; z <= zlast; z++) {
+    const int bf = (z - z0) & 1;
+    xpass(sIn[bf], sX[bf]);
+    if (z + 1 <= zlast) commit(sIn[bf ^ 1]);
+    __syncthreads();
+    if (z + 2 <= zlast) request(z + 2);
+    ypass(sX[bf], w);
+    const int a = z % P;
+    if (a != 0) {
+#pragma unroll
+      for (int j = 0; j < RY; j++) {
+#pragma unroll
+        for (int l = 0; l < n; l++) acc[j][l] += sM[l * n + a] * w[j];
+      }
+    } else {
+      // vertex plane: completes element z / P - 1 (none at z0), starts z / P
+      const int e = z / P - 1;
+      if (z > z0) {
+#pragma unroll
+        for (int j = 0; j < RY; j++) {
+#pragma unroll
+          for (int l = 0; l < n; l++) acc[j][l] += M(l, P) * w[j];
+        }
+        if (e >= ez_lo) {
+#pragma unroll
+          for (int l = 0; l < P; l++) {
+#pragma unroll
+            for (int j = 0; j < RY; j++) emit(e * P + l, j, acc[j][l]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < RY; j++) {
+        carry[j] = z > z0 ? acc[j][P] : T(0);
+#pragma unroll
+        for (int l = 0; l < n; l++) acc[j][l] = M(l, 0) * w[j];
+        acc[j][0] += carry[j];
+      }
+    }
+  }
+  if (ez_hi == m.nz) {  // the final vertex plane: element nz - 1 only
+#pragma unroll
+    for (int j = 0; j < RY; j++) emit(Nz - 1, j, carry[j]);
   }
   if (RED) block_partial_t<NT>(dot, red, s_red);
 }
@@ -1427,23 +1577,42 @@ int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, con
                       : launch_tangent_q<P, P + 2, T>(m, mu, lam, ulin, state, msr, v, y, mask, pu, skip, st);
 }
 
-template <int P, int Q, typename T>
-int launch_mass_q(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
-                  const int *skip, hipStream_t st) {
-  using D = MassDims<P, (int)sizeof(T)>;
-  dim3 grid(((m.nx + D::NE - 1) / D::NE) * m.ny * m.nz), block(D::NT);
-  if (do_red)
-    hipLaunchKernelGGL((k_mass<P, Q, T, true>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
-  else
-    hipLaunchKernelGGL((k_mass<P, Q, T, false>), grid, block, 0, st, m, rho, v, y, mask, red, skip);
-  if (m.stage && launch_stage_gather<T>(P, m, D::NE, D::TX, D::TILE, mask, y, skip, st)) return -1;
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+// Mass-kernel grid: z chunks sized so that the grid fits in the blocks the
+// device holds at once (occupancy x compute units, queried once per
+// instantiation on the current device).
+template <int P, typename T>
+KronGrid mass_grid_t(const MeshK<T> &m) {
+  static int cap = 0;
+  if (!cap) {
+    int nb = 0, cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mass<P, T, false>,
+                                                     KronDims<P, (int)sizeof(T)>::NT, 0) !=
+            hipSuccess)
+      nb = cus = 0;
+    cap = nb * cus > 0 ? nb * cus : 1024;
+  }
+  return kron_grid<KronDims<P, (int)sizeof(T)>>(m.nx, m.ny, m.nz, cap);
 }
+template <int P, typename T>
+int mass_blocks_t(const MeshK<T> &m) {
+  return mass_grid_t<P, T>(m).blocks();
+}
+
 template <int P, typename T>
 int launch_mass_t(const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red, int do_red,
                   const int *skip, hipStream_t st) {
-  return m.Q == P + 1 ? launch_mass_q<P, P + 1, T>(m, rho, v, y, mask, red, do_red, skip, st)
-                      : launch_mass_q<P, P + 2, T>(m, rho, v, y, mask, red, do_red, skip, st);
+  using D = KronDims<P, (int)sizeof(T)>;
+  const KronGrid g = mass_grid_t<P, T>(m);
+  const T rs = rho * m.detJ;
+  if (do_red)
+    hipLaunchKernelGGL((k_mass<P, T, true>), dim3(g.blocks()), dim3(D::NT), 0, st, m, rs, v, y,
+                       mask, red, skip, g);
+  else
+    hipLaunchKernelGGL((k_mass<P, T, false>), dim3(g.blocks()), dim3(D::NT), 0, st, m, rs, v, y,
+                       mask, red, skip, g);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int P, int Q, typename T>
@@ -1508,6 +1677,8 @@ template int launch_tangent_t<SDME_P, float>(const MeshK<float> &, const double 
                                              const float *, const float *, float, const float *,
                                              float *, int, const PUpd<float> *, const int *,
                                              hipStream_t);
+template int mass_blocks_t<SDME_P, double>(const MeshK<double> &);
+template int mass_blocks_t<SDME_P, float>(const MeshK<float> &);
 template int launch_mass_t<SDME_P, double>(const MeshK<double> &, double, const double *, double *,
                                            int, Reduce, int, const int *, hipStream_t);
 template int launch_mass_t<SDME_P, float>(const MeshK<float> &, float, const float *, float *, int,

@@ -75,27 +75,62 @@ struct Dims {
   static constexpr int TILE = 3 * n * n * TX;
 };
 
-// Mass action on affine hexahedra: the element mass is rho detJ times the
-// Kronecker product of the 1D mass of the rule, Mq[a][b] = sum_q w_q B[q][a]
-// B[q][b], in each direction.  A block owns a run of NE consecutive elements
-// of one x-row and applies the 1D matrices to its tile [3][n][n][TX] of slots
-// (along x assembled over the run).  Two tiles (input, output) of at most
-// 48 KiB together; NE gives runs of about 32 slots.
+// Mass action on affine hexahedra with one density: the element mass is
+// rho detJ (Mq x Mq x Mq), Mq[a][b] = sum_q w_q B[q][a] B[q][b] the 1D mass
+// of the rule, so the assembled mass is rho detJ times the Kronecker product
+// of the three assembled 1D masses (banded: a slot couples with the slots of
+// the elements it belongs to).  A block owns a box of output slots: EX
+// elements along x (one lane per slot), EY along y (each wave RY rows of one
+// element) and a chunk of elements along z, which it marches through plane by
+// plane: the x and y passes of each input plane run through LDS, the z pass
+// accumulates in registers per element, and every output slot is written
+// once (no atomics).  Element indices run to n_d inclusive along each
+// direction: the last "element" n_d only owns the final vertex slot.
 template <int P_, int WORD>
-struct MassDims {
+struct KronDims {
   static constexpr int P = P_, n = P_ + 1;
-  static constexpr int LINES = 3 * n * n;
-  static constexpr int NT = 256;
-  static constexpr int cap_slots() { return 49152 / (2 * WORD * LINES); }
-  static constexpr int ne_fit() {
-    int ne = 32 / P > 0 ? 32 / P : 1;
-    while (ne > 1 && ne * P + 1 > cap_slots()) ne--;
-    return ne;
-  }
-  static constexpr int NE = ne_fit();
-  static constexpr int TX = NE * P + 1;
-  static constexpr int TILE = LINES * TX;
+  // 8 waves per block in FP32, 4 in FP64 (measured at 47^3, P = 4)
+#ifdef SDME_KRON_WAVES
+  static constexpr int WAVES = SDME_KRON_WAVES;
+#else
+  static constexpr int WAVES = WORD == 4 ? 8 : 4;
+#endif
+  static constexpr int NT = 64 * WAVES;
+  static constexpr int EX = 64 / P_, TX = EX * P_;
+  // rows per wave: one element's P rows, or half of them (FP64, P = 8:
+  // register budget of the z accumulators)
+  static constexpr int RY = (WORD == 8 && P_ == 8) ? 4 : P_;
+  static constexpr int GPE = P_ / RY, EY = WAVES / GPE, TY = EY * P_;
+  // input plane (x0 - P .. x0 + TX, y0 - P .. y0 + TY) and x-filtered plane;
+  // row pitches in 16-byte units (an element's slots are read and written
+  // with wide LDS accesses where they are 16-byte aligned)
+  static constexpr int IX = TX + P_ + 1, IY = TY + P_ + 1;
+  static constexpr int VW = 16 / WORD;
+  static constexpr int IXP = (IX + VW - 1) / VW * VW, TXP = (TX + VW - 1) / VW * VW;
+  static constexpr int NLD = (IX * IY + NT - 1) / NT;
+  // an element's P slots start 16-byte aligned in a row when P is a
+  // multiple of the vector width
+  static constexpr bool VEC = P_ % VW == 0;
 };
+// Launch shape of the mass kernel: x, y tiles and z chunks of cz elements,
+// as many chunks as keep the grid within `target` blocks (the blocks the
+// device holds at once, so that every block starts at once).
+struct KronGrid {
+  int nxt, nyt, nzc, cz;
+  __host__ __device__ int blocks() const { return nxt * nyt * nzc * 3; }
+};
+template <class D>
+__host__ __device__ inline KronGrid kron_grid(int nx, int ny, int nz, int target) {
+  KronGrid g;
+  g.nxt = (nx + D::EX) / D::EX;  // elements 0 .. nx
+  g.nyt = (ny + D::EY) / D::EY;
+  const int base = g.nxt * g.nyt * 3;
+  int nzc = target / base;
+  nzc = nzc < 1 ? 1 : (nzc > nz ? nz : nzc);
+  g.cz = (nz + nzc - 1) / nzc;
+  g.nzc = (nz + g.cz - 1) / g.cz;
+  return g;
+}
 
 // Mesh parameters passed by value to every kernel.
 template <typename T>

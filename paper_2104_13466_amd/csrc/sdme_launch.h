@@ -29,9 +29,14 @@ template <typename T>
 int launch_tangent(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *ulin,
                    const T *state, T msr, const T *v, T *y, int mask, const PUpd<T> *pu,
                    const int *skip, hipStream_t st);
+// y = rho M v, every slot of y written (constrained slots as zero with
+// mask); do_red: block partials of v^T y in red.partials[2 b], over the
+// mass_blocks(P, m) blocks of the launch.
 template <typename T>
 int launch_mass(int P, const MeshK<T> &m, T rho, const T *v, T *y, int mask, Reduce red,
                 int do_red, const int *skip, hipStream_t st);
+template <typename T>
+int mass_blocks(int P, const MeshK<T> &m);
 template <typename T>
 int launch_diag(int P, const MeshK<T> &m, const double *mu, const double *lam, const T *state,
                 T msr, T *d, int mask, hipStream_t st);
@@ -42,10 +47,9 @@ int launch_matgrad(int P, const MeshK<double> &m, const double *u, const double 
 // Blocks of an element kernel launch with Q points per direction (grad =
 // false: the value-only mass kernel).
 int elem_blocks(int P, int Q, int word, int nx, int ny, int nz, bool grad = true);
-// Words of one block's output tile (the staging stride of the deterministic
-// assembly) and the elements per block.
+// Words of one block's output tile (the staging stride of the ordered
+// assembly; 0 for the mass kernel, which writes every slot once).
 int elem_tile_words(int P, int Q, int word, bool grad = true);
-int elem_run(int P, int Q, int word, bool grad = true);
 // Deterministic assembly: y[slot] = sum of the staged tiles holding the slot
 // (runs of ne elements, tiles of tx slots along x, stride tile words), in
 // ascending block order; constrained slots get 0 with mask.
