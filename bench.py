@@ -146,6 +146,37 @@ def kernel_table(ctx, mat, u0):
     return rows
 
 
+def mass_roofline(ctx):
+    """The mass action (Kronecker stencil) on the workload mesh: per-launch
+    time (HIP events on the stream the library launches on, 10 launches after
+    2 warm-ups) against its algorithmic bytes, v read and y written once."""
+    import torch
+
+    from paper_2104_13466_amd.sdme import FP32, FP64
+    N = 3 * ctx.Nn
+    out = {}
+    for prec, dt, word in ((FP32, torch.float32, 4), (FP64, torch.float64, 8)):
+        v = torch.rand(N, dtype=dt, device="cuda")
+        y = torch.zeros_like(v)
+        for _ in range(2):
+            ctx.mass_apply(1.0, prec, v, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            ctx.mass_apply(1.0, prec, v, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        gbs = 2 * word * N / (ms * 1e-3) / 1e9
+        out["k_mass_" + ("fp32" if prec == FP32 else "fp64")] = {
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms, 4),
+            "algorithmic_bytes_per_launch": 2 * word * N}
+        log("mass %s %.4f ms %.0f GB/s" % ("fp32" if prec == FP32 else "fp64", ms, gbs))
+    return out
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A plain device copy of known size (nbytes read + nbytes written per
     launch): the reference that scales the HBM byte counters of the kernels."""
@@ -963,6 +994,7 @@ def main():
                   "runs_ms": [round(1e3 * t, 1) for t in times]},
         "speedup_mixed_vs_fp64": round(1e3 * t64 / ms_step, 3),
         "max_rel_diff_increment_mixed_vs_fp64": dd}
+    result["other_kernels"] = mass_roofline(ctx)
     if not a.no_solve:
         result["newton_pcg"] = full_solve(ctx, mat, u0, a)
     if not a.no_cpu_baseline:

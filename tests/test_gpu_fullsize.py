@@ -12,7 +12,10 @@ sample; for the internal force of the near-equilibrium state the FP64 bound is
 relative to the sum of absolute element contributions.  The PCG operator with
 the fused direction update (the kernel the benchmark times) is checked through
 two iterations of the mixed-precision PCG against the oracle's FP64 CG on the
-whole mesh."""
+whole mesh.  The mass action (a z-marching stencil whose blocks own chunks of
+element layers along z) is sampled on the seeded elements and on a whole
+column of elements along z, which crosses every chunk boundary whatever the
+chunk size the device's occupancy gives."""
 import numpy as np
 import pytest
 
@@ -187,3 +190,25 @@ def test_fullsize_mixed_pcg_fused_operator(full):
     xr, its, _ = osv.pcg(pb.A(u, 0.0), b, pb.diag(u, 0.0), 1e-30, 2)
     assert its == 2
     assert relerr(full.host(x), xr) < TOL32
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_fullsize_masked_mass(full, prec):
+    t = full.torch
+    w = full.w
+    dt = t.float64 if prec == FP64 else t.float32
+    v = inputs.uniform(w["seed"], full.N, -1, 1, stream=7)
+    if prec == FP32:
+        v = v.astype(np.float32).astype(np.float64)
+    y = t.zeros(full.N, dtype=dt, device="cuda")
+    full.ctx.mass_apply(1.3, prec, full.dev(v, dt), y, flags=MASK_BC)
+    keep_v, keep_e = full.v, full.elems
+    full.v = v
+    col = np.array([(full.n[0] // 2, full.n[1] - 1, ez) for ez in range(full.n[2])])
+    full.elems = np.concatenate([keep_e, col])
+    try:
+        got, ref, _ = full.sample(full.host(y),
+                                  lambda pb, u, vv, m: m * pb.mesh.mass_apply(1.3, m * vv))
+    finally:
+        full.v, full.elems = keep_v, keep_e
+    assert relerr(got, ref) < (TOL64 if prec == FP64 else TOL32)
