@@ -163,6 +163,13 @@ int sdme_context_bytes(const sdme_ctx *ctx, size_t *dev_bytes, size_t *host_byte
 int sdme_bind(sdme_ctx *ctx, void *dev_block, size_t dev_bytes, void *host_block,
               size_t host_bytes, void *stream);
 
+/* The element named by the last SDME_EJAC: the smallest index of an element
+ * with det F <= 0 at a Gauss point in the last call that checked the
+ * Jacobian (SDME_CHECK_JAC, the Newton drivers), or -1 when that call found
+ * none.  Host-only; element index e = (ez ny + ey) nx + ex.  Errors:
+ * SDME_EINVAL (NULL). */
+int sdme_jac_element(const sdme_ctx *ctx, int64_t *element);
+
 /* out[0] = Nn (slots per component), out[1] = E (elements),
  * out[2] = Gauss points (E*Q^3), out[3] = words of linearisation state per
  * Gauss point (10: F^-1 and mu - lambda ln J). */

@@ -17,7 +17,8 @@ HIP_SOURCES = ["elem_dispatch.hip", "vec_kernels.hip", "load_kernels.hip", "cond
 ORDERS = range(1, 9)
 HOST_SOURCES = ["basis.cpp"]
 
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     # packed FP32 VALU ops stay off (hipcc device-side feature flag)
@@ -57,7 +58,9 @@ def build(verbose=False, jobs=None):
             if verbose and out.strip():
                 print(out)
     tmp = OUT + ".tmp%d" % os.getpid()
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx",
+          "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, OUT)
     return OUT
 

@@ -2,9 +2,11 @@
 // loops (host side; every arithmetic step runs in the kernels of
 // elem_kernels.hip and vec_kernels.hip).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -47,6 +49,7 @@ struct sdme_ctx {
   PcgDev *h_pcg = nullptr;
   double *h_res = nullptr;
   int *h_flag = nullptr;
+  int64_t jac_element = -1;  // from the last read of the status words
   MeshK<double> m64;
   MeshK<float> m32;
   // the meshes of the mass operator: the same as m64, m32, or (mass_rule 1)
@@ -81,6 +84,16 @@ struct Timer {
 };
 
 Reduce red_at(sdme_ctx *c, int slot) { return Reduce{c->partials, c->counter, c->results + slot}; }
+
+// roctx range around a driver phase (Newton iteration, time step, linear
+// solve): host-side markers that rocprofv3 --marker-trace records beside the
+// kernels; without a profiler attached the calls return at once.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 template <typename T>
 const MeshK<T> &mk(const sdme_ctx *c);
@@ -120,14 +133,23 @@ int lerr(int r) { return r == 0 ? SDME_OK : (r == -2 ? SDME_EINVAL : SDME_EDEVIC
 
 bool valid_prec(int p) { return p == SDME_FP64 || p == SDME_FP32; }
 
+// Status words on the device: flag[0] = 1 once det F <= 0 was met at a
+// Gauss point, flag[1] = the smallest index of an element where it was
+// (INT_MAX: none).  read_flag keeps that element for sdme_jac_element.
 int read_flag(sdme_ctx *c, hipStream_t st) {
-  if (hipMemcpyAsync(c->h_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+  if (hipMemcpyAsync(c->h_flag, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
     return SDME_EDEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return SDME_EDEVICE;
-  return *c->h_flag ? SDME_EJAC : SDME_OK;
+  c->jac_element = (c->h_flag[0] && c->h_flag[1] != INT_MAX) ? c->h_flag[1] : -1;
+  return c->h_flag[0] ? SDME_EJAC : SDME_OK;
 }
 
-int clear_flag(sdme_ctx *c, hipStream_t st) { return lerr(launch_fill<int>(c->flag, 0, 1, st)); }
+int clear_flag(sdme_ctx *c, hipStream_t st) {
+  return lerr(launch_fill<int>(c->flag, 0, 1, st) || launch_fill<int>(c->flag + 1, INT_MAX, 1, st)
+                  ? -1
+                  : 0);
+}
 
 // ||x||^2 and x.y in double (synchronises); returns via out[0] = x.y, out[1] = y.y
 template <typename T>
@@ -347,6 +369,7 @@ int solve_linear(sdme_ctx *c, const sdme_material *mat, int prec, const double *
                  double shift, bool mass_only, const double *b, double *x, double rtol, int maxit,
                  double inner_rtol, LinWs &w, sdme_stats *stats, hipStream_t st,
                  int *its_out = nullptr) {
+  Range range("sdme_pcg");
   int64_t N = 3 * c->Nn;
   int P = c->P;
   // masked right-hand side
@@ -456,7 +479,7 @@ static void plan_blocks(sdme_ctx *c) {
   b.o_tm32 = take(sizeof(float) * TSM);
   b.o_t64 = take(sizeof(double) * TS);
   b.o_t32 = take(sizeof(float) * TS);
-  b.o_flag = take(sizeof(int));
+  b.o_flag = take(2 * sizeof(int));
   b.o_pcg = take(2 * sizeof(PcgDev));
   b.o_part = take(sizeof(double) * 2 * (size_t)nblk);
   b.o_cnt = take(sizeof(unsigned) * 4);
@@ -601,6 +624,12 @@ extern "C" int sdme_context_bytes(const sdme_ctx *c, size_t *dev_bytes, size_t *
   if (!c || !dev_bytes || !host_bytes) return SDME_EINVAL;
   *dev_bytes = c->plan.dev_bytes;
   *host_bytes = c->plan.host_bytes;
+  return SDME_OK;
+}
+
+extern "C" int sdme_jac_element(const sdme_ctx *c, int64_t *element) {
+  if (!c || !element) return SDME_EINVAL;
+  *element = c->jac_element;
   return SDME_OK;
 }
 
@@ -1226,6 +1255,7 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
   double alpha = 1.0;
   int halvings = 0;
   for (int k = 0;; k++) {
+    Range range("sdme_newton_iteration");
     if ((rc = clear_flag(c, st))) return rc;
     if (launch_fill<double>(R, 0.0, N, st) ||
         launch_force<double>(c->P, c->m64, mat->mu, mat->lam, u, R, state64, 1, st))
@@ -1411,6 +1441,7 @@ extern "C" int sdme_explicit_step(sdme_ctx *c, const sdme_material *mat, int pre
       !(dt > 0) || !(mass_rtol > 0) || (!u_prev && !v0) || !(mat->rho > 0))
     return SDME_EINVAL;
   if (int rc_ = ensure_device(c)) return rc_;
+  Range range("sdme_explicit_step");
   Timer tm;
   hipStream_t st = S(stream);
   ExWs w;

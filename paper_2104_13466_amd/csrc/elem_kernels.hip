@@ -792,7 +792,10 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
       accum_at<K, T, true, false>(s_tab, q3, f, mv, A);
     }
   }
-  if (bad && s.valid) atomicOr(m.flag, 1);
+  if (bad && s.valid) {
+    atomicOr(m.flag, 1);
+    atomicMin(m.flag + 1, s.e);
+  }
   if (OUT) {
     double dummy = 0;
     transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_row, R, mask != 0, (const T *)nullptr,
@@ -972,7 +975,10 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
       point(q3, G, G[9]);
     }
   }
-  if (REC && bad && s.valid) atomicOr(m.flag, 1);
+  if (REC && bad && s.valid) {
+    atomicOr(m.flag, 1);
+    atomicMin(m.flag + 1, s.e);
+  }
   double dot = 0;
   transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_row, y, mask != 0,
                                    (const T *)nullptr, dot);

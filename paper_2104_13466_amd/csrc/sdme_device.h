@@ -142,7 +142,8 @@ struct MeshK {
   T ih[3];       // 2 / h_J  (reference-to-physical derivative scale)
   T detJ;        // h_x h_y h_z / 8
   const T *tab;  // device basis tables (layout of Dims)
-  int *flag;     // device status word: set to 1 when det F <= 0
+  int *flag;     // device status words: [0] set to 1 when det F <= 0 at a Gauss
+                 // point, [1] the smallest index of an element where it was
   // deterministic assembly: element kernels store their blocks' output tiles
   // (or element vectors) here and a gather kernel sums every slot's
   // contributions in a fixed order; nullptr: hardware atomics

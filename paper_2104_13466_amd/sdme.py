@@ -70,6 +70,7 @@ SIGNATURES = {
     "sdme_context_bytes": ([_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)], _i),
     "sdme_bind": ([_vp, _vp, _sz, _vp, _sz, _vp], _i),
     "sdme_sizes": ([_vp, ctypes.POINTER(_i64)], _i),
+    "sdme_jac_element": ([_vp, ctypes.POINTER(_i64)], _i),
     "sdme_gather_indices": ([_vp, ctypes.POINTER(ctypes.c_int32)], _i),
     "sdme_dirichlet_flags": ([_vp, ctypes.POINTER(ctypes.c_uint8)], _i),
     "sdme_affine_field": ([_vp, _dp, _dp, _dp], _i),
@@ -295,6 +296,13 @@ class Context:
         _chk(self.L.sdme_gather_indices(self.handle, out.ctypes.data_as(
             ctypes.POINTER(ctypes.c_int32))), "gather_indices")
         return out.reshape(self.E, -1)
+
+    def jac_element(self):
+        """Smallest element index with det F <= 0 found by the last call that
+        checked the Jacobian (CHECK_JAC, the Newton drivers), or None."""
+        e = ctypes.c_int64()
+        _chk(self.L.sdme_jac_element(self.handle, ctypes.byref(e)), "jac_element")
+        return None if e.value < 0 else int(e.value)
 
     def dirichlet_flags(self):
         out = np.zeros(3 * self.Nn, dtype=np.uint8)

@@ -216,6 +216,8 @@ def test_context_bytes_and_bind_checks():
     out_d, out_h = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.sdme_context_bytes(None, ctypes.byref(out_d), ctypes.byref(out_h)) == -1
     assert L.sdme_context_bytes(h, None, ctypes.byref(out_h)) == -1
+    # no checked call yet: no element named
+    assert c.jac_element() is None
     # unbound: every device entry point returns SDME_EINVAL
     assert L.sdme_mass_apply(h, 1.0, 0, p, p, 0, None) == -1
     m = sdme.Material()

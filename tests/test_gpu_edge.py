@@ -135,8 +135,41 @@ def test_status_inverted_element_with_check_jac():
     s = p.ctx.jacobi_pcg(p.mat, FP64, p.dev(inputs.uniform(3, p.N, -1, 1)), p.zeros(), u_lin=ud,
                          check=False)
     assert s["status"] == -5
+    assert p.ctx.jac_element() == 0  # every element is inverted: the first is named
     # the flag is cleared by the next checked call: a valid state passes
     p.ctx.internal_force(p.mat, FP64, p.dev(p.mask * p.rand(4, 1e-3)), R, flags=CHECK_JAC)
+    assert p.ctx.jac_element() is None
+
+
+@pytest.mark.parametrize("corner", ["first", "last"])
+def test_jac_element_names_the_inverted_element(corner):
+    # Lagrange-GLL basis at P = 2: the slot at a corner of the box is a node
+    # whose shape function lives in the corner element only.  Pushing that
+    # node across the element (5 h inwards along every axis) inverts that
+    # element and no other; the checked calls report it by index.
+    from paper_2104_13466_amd.sdme import CHECK_JAC, SdmeError
+    p = Pair((4, 3, 2), (1.0, 0.75, 0.5), 2, kind=ob.NODAL)
+    h = np.array([1.0 / 4, 0.75 / 3, 0.5 / 2])
+    Nx, Ny, Nz = (4 * 2 + 1, 3 * 2 + 1, 2 * 2 + 1)
+    Nn = Nx * Ny * Nz
+    u = np.zeros(p.N)
+    if corner == "first":
+        slot, sign, expect = 0, 1.0, 0
+    else:
+        slot, sign, expect = Nn - 1, -1.0, 4 * 3 * 2 - 1
+    for c in range(3):
+        u[c * Nn + slot] = sign * 5.0 * h[c]
+    ud = p.dev(u)
+    R = p.zeros()
+    with pytest.raises(SdmeError) as e:
+        p.ctx.internal_force(p.mat, FP64, ud, R, flags=CHECK_JAC)
+    assert e.value.code == -5
+    assert p.ctx.jac_element() == expect
+    with pytest.raises(SdmeError):
+        p.ctx.tangent_apply(p.mat, FP32, p.dev(inputs.uniform(5, p.N, -1, 1), p.torch.float32),
+                            p.zeros(p.torch.float32), u_lin=p.dev(u, p.torch.float32),
+                            flags=CHECK_JAC)
+    assert p.ctx.jac_element() == expect
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
