@@ -315,7 +315,8 @@ typedef struct {
   int outer;          /* FP64 defect-correction sweeps (mixed mode)           */
   int newton;         /* Newton iterations                                    */
   int mass_iterations;/* PCG iterations of mass solves (explicit, adjoint)    */
-  int pad;
+  int halvings;       /* Newton increments halved because the updated state   */
+                      /* inverted an element (damped Newton)                  */
   double rel_residual;/* final ||b - A x|| / ||b|| (FP64)                      */
   double newton_rel;  /* final ||psi|| / ||psi_0||                             */
   double time_ms;     /* wall time of the call                                */

@@ -1264,6 +1264,7 @@ int newton_loop(sdme_ctx *c, const sdme_material *mat, int prec, double *u, cons
       if (rc != SDME_EJAC || k == 0 || halvings >= 20) return rc;
       alpha *= 0.5;
       halvings++;
+      if (stats) stats->halvings++;
       if (launch_axpby(u, -alpha, du, 1.0, N, st)) return SDME_EDEVICE;
       k--;
       continue;

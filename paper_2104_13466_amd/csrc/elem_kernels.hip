@@ -1207,7 +1207,11 @@ __global__ __launch_bounds__((KronDims<P, (int)sizeof(T)>::NT)) void k_mass(
                      ((mb & 32768u) && zo == Nz - 1);
     const size_t gi = (size_t)zo * plane_sz + orow[j];
     const T o = con ? T(0) : val * rs;
-    yc[gi] = o;
+    // non-temporal stores in FP64 (4 % faster at 47^3, P = 4; 2 % slower in FP32)
+    if constexpr (sizeof(T) == 8)
+      __builtin_nontemporal_store(o, yc + gi);
+    else
+      yc[gi] = o;
     if (RED && !con) dot += (double)vp[gi] * (double)o;
   };
   // z march over the planes z0 .. zlast of elements e_start .. ez_hi - 1

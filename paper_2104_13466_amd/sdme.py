@@ -48,12 +48,13 @@ class Contact(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int), ("outer", ctypes.c_int),
-                ("newton", ctypes.c_int), ("mass_iterations", ctypes.c_int), ("pad", ctypes.c_int),
+                ("newton", ctypes.c_int), ("mass_iterations", ctypes.c_int),
+                ("halvings", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("newton_rel", ctypes.c_double),
                 ("time_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _LIB = None

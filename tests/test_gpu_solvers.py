@@ -281,3 +281,28 @@ def test_affine_patch_reproduced_with_gll_rule():
     st = p.ctx.newton_static(p.mat, FP64, ud, newton_rtol=1e-10, pcg_rtol=1e-10)
     assert st["newton_rel"] <= 1e-10
     assert relerr(p.host(ud), ua) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_damped_newton_halves_inverting_increments(prec):
+    # Large simple shear of the top layer: Lagrange-GLL basis, P = 2, unit
+    # cube of 2x2x2 elements, both z faces prescribed, the top face moved by
+    # 1.2 along x and every other slot at zero (the top element layer starts
+    # in a volume-preserving shear of 2.4).  The tangent there is not
+    # positive definite (truncated Newton-CG) and full Newton increments
+    # invert elements (in the oracle's replay of this iteration too), so the
+    # driver halves them; it still reaches equilibrium, which the oracle's
+    # residual confirms.
+    bits = inputs.face_bits(4) | inputs.face_bits(5)
+    p = Pair((2, 2, 2), (1.0, 1.0, 1.0), 2, kind=ob.NODAL, dirichlet=bits)
+    Nd = 5
+    u0 = np.zeros(p.N)
+    u0[(Nd - 1) * Nd * Nd:Nd * Nd * Nd] = 1.2  # x component of the top face slots
+    ud = p.dev(u0)
+    st = p.ctx.newton_static(p.mat, prec, ud, newton_rtol=1e-8, pcg_rtol=1e-8, max_newton=60)
+    assert st["halvings"] >= 1
+    assert st["newton_rel"] <= 1e-8
+    u = p.host(ud)
+    assert np.array_equal(u[p.mask == 0], u0[p.mask == 0])
+    r0 = np.linalg.norm(p.mask * p.pb.R(u0))
+    assert np.linalg.norm(p.mask * p.pb.R(u)) <= 1e-7 * r0
