@@ -1590,19 +1590,20 @@ int launch_tangent_t(const MeshK<T> &m, const double *mu, const double *lam, con
 // Mass-kernel grid: z chunks sized so that the grid fits in the blocks the
 // device holds at once (occupancy x compute units, queried once per
 // instantiation on the current device).
+// (The capacity is taken on the device current at the first launch and kept
+// for the process: the library runs on one GPU model.)
 template <int P, typename T>
 KronGrid mass_grid_t(const MeshK<T> &m) {
-  static int cap = 0;
-  if (!cap) {
+  static const int cap = [] {
     int nb = 0, cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mass<P, T, false>,
                                                      KronDims<P, (int)sizeof(T)>::NT, 0) !=
             hipSuccess)
-      nb = cus = 0;
-    cap = nb * cus > 0 ? nb * cus : 1024;
-  }
+      return 1024;
+    return nb * cus > 0 ? nb * cus : 1024;
+  }();
   return kron_grid<KronDims<P, (int)sizeof(T)>>(m.nx, m.ny, m.nz, cap);
 }
 template <int P, typename T>
