@@ -35,7 +35,11 @@
  *  - stream is a hipStream_t passed as void* (NULL = default stream).  Calls
  *    are asynchronous on that stream unless documented as synchronising
  *    (solvers and drivers read convergence scalars back and return after the
- *    solve; their stats are valid on return).
+ *    solve; their stats are valid on return).  Calls on one context share
+ *    its device block (reduction partials, solver scalars, status words and,
+ *    with SDME_ASSEMBLY_ORDERED, the staging array): they must not overlap,
+ *    i.e. issue them on one stream or order the streams; the host object is
+ *    not thread-safe.
  *  - Dirichlet DOFs (faces/components set in sdme_mesh_desc.dirichlet) carry
  *    their prescribed values inside displacement vectors.  With
  *    SDME_MASK_BC, operators treat constrained DOFs of their input direction
