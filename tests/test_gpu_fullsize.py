@@ -32,10 +32,10 @@ NSAMPLE = 24
 
 
 class Full:
-    def __init__(self):
+    def __init__(self, name="compress_p4", nsample=NSAMPLE):
         import torch
         self.torch = torch
-        w = inputs.WORKLOADS["compress_p4"]
+        w = inputs.WORKLOADS[name]
         self.w = w
         self.n, self.L, self.P = w["n"], w["L"], w["P"]
         self.ctx = Context(self.n, self.L, self.P, basis=w["kind"], dirichlet=w["dirichlet"])
@@ -56,7 +56,7 @@ class Full:
         self.N = self.u.size
         self.grid = (self.n[2] * self.P + 1, self.n[1] * self.P + 1, self.n[0] * self.P + 1)
         # sampled elements: seeded, including the clamped and the moved faces
-        r = inputs.uniform(w["seed"], 3 * NSAMPLE, stream=11).reshape(NSAMPLE, 3)
+        r = inputs.uniform(w["seed"], 3 * nsample, stream=11).reshape(nsample, 3)
         e = (r * np.array(self.n)).astype(int)
         e[0] = (0, 0, 0)
         e[1] = (self.n[0] - 1, self.n[1] - 1, self.n[2] - 1)
@@ -212,3 +212,29 @@ def test_fullsize_masked_mass(full, prec):
     finally:
         full.v, full.elems = keep_v, keep_e
     assert relerr(got, ref) < (TOL64 if prec == FP64 else TOL32)
+
+
+@pytest.mark.parametrize("name", ["compress_p2", "compress_p6", "compress_p8"])
+def test_fullsize_sweep_orders(name):
+    # the other members of the polynomial-order sweep at their full sizes
+    # (94^3, 31^3, 23^3 elements, about 2e7 DOF each): the FP32 masked
+    # stored-state tangent (the PCG operator) and the FP64 masked mass on
+    # every slot of 8 sampled elements (two of them the mesh's corners)
+    f = Full(name, nsample=8)
+    t = f.torch
+    f32 = t.float32
+    u32, v32 = f.u.astype(np.float32), f.v.astype(np.float32)
+    st = t.empty(f.ctx.nqp * 10, dtype=f32, device="cuda")
+    f.ctx.linearize(f.mat, FP32, f.dev(u32, f32), st)
+    y = t.zeros(f.N, dtype=f32, device="cuda")
+    f.ctx.tangent_apply(f.mat, FP32, f.dev(v32, f32), y, state=st, flags=MASK_BC)
+    del st
+    f.u, f.v = u32.astype(np.float64), v32.astype(np.float64)
+    got, ref, _ = f.sample(f.host(y), lambda pb, u, v, m: m * pb.mesh.tangent_apply(
+        pb.mu, pb.lam, u, m * v))
+    assert relerr(got, ref) < TOL32
+    ym = t.zeros(f.N, dtype=t.float64, device="cuda")
+    f.ctx.mass_apply(0.7, FP64, f.dev(f.v, t.float64), ym, flags=MASK_BC)
+    got, ref, _ = f.sample(f.host(ym), lambda pb, u, v, m: m * pb.mesh.mass_apply(0.7, m * v))
+    assert relerr(got, ref) < TOL64
+    f.ctx.close()
