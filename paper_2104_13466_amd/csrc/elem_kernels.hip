@@ -1015,8 +1015,7 @@ __global__ __launch_bounds__((KronDims<P, (int)sizeof(T)>::NT)) void k_mass(
   constexpr int n = D::n, NT = D::NT, EX = D::EX, TX = D::TX, RY = D::RY, GPE = D::GPE,
                 IX = D::IX, IY = D::IY, IXP = D::IXP, TXP = D::TXP, NLD = D::NLD;
   constexpr int NXI = (EX * IY + NT - 1) / NT;  // x-pass items per thread
-  // the 1D mass in registers where it is small, else read from LDS
-  constexpr bool MQR = n * n * (int)sizeof(T) <= 100;
+  constexpr bool MQR = D::MQR;
   if (skip && *skip) return;
   // input and x-filtered planes, two of each (plane z uses buffer z & 1)
   __shared__ __align__(16) T sIn[2][IY * IXP];

@@ -89,17 +89,25 @@ struct Dims {
 template <int P_, int WORD>
 struct KronDims {
   static constexpr int P = P_, n = P_ + 1;
-  // 8 waves per block in FP32, 4 in FP64 (measured at 47^3, P = 4)
+  // Waves per block: 12 where the kernel's registers fit 3 waves per SIMD
+  // per block (FP32 P <= 5, FP64 P <= 4), else 8 (FP32) or 4 (FP64)
+  // (measured at ~2e7 DOF for P = 2, 4, 6).  MQR: the 1D mass held in
+  // registers (where they are free at that occupancy), else read from LDS.
 #ifdef SDME_KRON_WAVES
   static constexpr int WAVES = SDME_KRON_WAVES;
 #else
-  static constexpr int WAVES = WORD == 4 ? 8 : 4;
+  static constexpr int WAVES = WORD == 4 ? (P_ <= 5 ? 12 : 8) : (P_ <= 4 ? 12 : 4);
+#endif
+#ifdef SDME_KRON_MQR
+  static constexpr bool MQR = SDME_KRON_MQR;
+#else
+  static constexpr bool MQR = WORD == 4 ? P_ <= 7 : P_ <= 2;
 #endif
   static constexpr int NT = 64 * WAVES;
   static constexpr int EX = 64 / P_, TX = EX * P_;
-  // rows per wave: one element's P rows, or half of them (FP64, P = 8:
-  // register budget of the z accumulators)
-  static constexpr int RY = (WORD == 8 && P_ == 8) ? 4 : P_;
+  // rows per wave: one element's P rows, or half of them at P = 8 (register
+  // budget of the z accumulators)
+  static constexpr int RY = P_ == 8 ? 4 : P_;
   static constexpr int GPE = P_ / RY, EY = WAVES / GPE, TY = EY * P_;
   // input plane (x0 - P .. x0 + TX, y0 - P .. y0 + TY) and x-filtered plane;
   // row pitches in 16-byte units (an element's slots are read and written

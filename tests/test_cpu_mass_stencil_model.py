@@ -19,10 +19,10 @@ NT_WAVE = 64
 
 def dims(P, word):
     n = P + 1
-    waves = 8 if word == 4 else 4
+    waves = (12 if P <= 5 else 8) if word == 4 else (12 if P <= 4 else 4)
     EX = 64 // P
     TX = EX * P
-    RY = 4 if (word == 8 and P == 8) else P
+    RY = 4 if P == 8 else P
     GPE = P // RY
     EY = waves // GPE
     TY = EY * P
