@@ -101,7 +101,7 @@ struct KronDims {
 #ifdef SDME_KRON_MQR
   static constexpr bool MQR = SDME_KRON_MQR;
 #else
-  static constexpr bool MQR = WORD == 4 ? P_ <= 7 : P_ <= 2;
+  static constexpr bool MQR = WORD == 4 ? P_ <= 7 : P_ <= 3;
 #endif
   static constexpr int NT = 64 * WAVES;
   static constexpr int EX = 64 / P_, TX = EX * P_;
