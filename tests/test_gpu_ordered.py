@@ -239,3 +239,23 @@ def test_resumed_explicit_run_is_bitwise_the_uninterrupted_one():
     saved = (q.host(prev), q.host(cur))
     _, resumed = run(3, q.dev(saved[0]), q.dev(saved[1]))
     assert same_bits(q.host(full), q.host(resumed))
+
+
+def test_condensed_solve_repeats_exactly():
+    # the condensed solve (two operator actions and the interior solves per
+    # iteration) on an ordered context: twice the same bits, and the full
+    # Jacobi-PCG solution to the solve tolerance
+    p = Pair((9, 3, 2), (1.5, 0.75, 0.5), 3, kind=ob.SDME_H, dirichlet=inputs.face_bits(0),
+             ordered=True)
+    u = p.mask * p.rand(21, 0.001)
+    b = p.dev(p.mask * inputs.uniform(22, p.N, -1, 1))
+    runs = []
+    for _ in range(2):
+        x = p.zeros()
+        s = p.ctx.condensed_pcg(p.mat, b, x, u_lin=p.dev(u), mass_shift=50.0, rtol=1e-11)
+        runs.append((s, p.host(x)))
+    assert runs[0][0]["iterations"] == runs[1][0]["iterations"]
+    assert same_bits(runs[0][1], runs[1][1])
+    xf = p.zeros()
+    p.ctx.jacobi_pcg(p.mat, FP64, b, xf, u_lin=p.dev(u), mass_shift=50.0, rtol=1e-11)
+    assert relerr(runs[0][1], p.host(xf)) < 1e-8
