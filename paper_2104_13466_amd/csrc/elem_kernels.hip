@@ -41,7 +41,10 @@ struct EK {
                        TSX = LW + Dm::Q;
   // shared memory words of a block: row offsets, per-element regions, the
   // tile, tables
-  static constexpr int SMEM = RW + NE * SE + TILEP + TSX;
+  // x-face contributions of the transposed xi1 stage, [3 n n][NE] (see
+  // stage1t_tile)
+  static constexpr int FACEW = 3 * n * n * NE, FACEP = Dm::rup(FACEW);
+  static constexpr int SMEM = RW + NE * SE + TILEP + FACEP + TSX;
   // Stored-state tangent action: PIPE selects two named buffers of
   // Gauss-point slabs requested ahead (the first two before the forward
   // contractions); otherwise one slab is prefetched per step.  Chosen by
@@ -601,11 +604,13 @@ __device__ __forceinline__ void stage2t(const T *sB, const T *sD, const T *sg, T
 }
 
 // Transposed xi1 contraction of component comp, thread (a = i1, b = i2),
-// added into the block's output tile (LDS atomics: neighbouring elements of
-// the run share their x-faces).
+// into the block's output tile.  Slots a < P of the element are its own in
+// the tile (plain stores, no zeroing needed); slot a = P is slot 0 of the
+// next element of the run, kept in face[row][le] for add_faces.  (Adding
+// every slot with LDS atomics into a zeroed tile was 15-39 % slower.)
 template <class K, typename T, bool GRAD>
 __device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *sB, const T *sD,
-                                             const T *st, T *tile) {
+                                             const T *st, T *tile, T *face) {
   constexpr int n = K::n, Q = K::Dm::Q, P = K::Dm::P, TX = K::TX, QP = K::Dm::QP;
   if (s.valid && s.i1 < n && s.i2 < n) {
     T cb[Q], cd[Q];
@@ -623,8 +628,32 @@ __device__ __forceinline__ void stage1t_tile(const Slab &s, int comp, const T *s
         val += cb[q] * h0[q];
         if (GRAD) val += cd[q] * h1[q];
       }
-      atomicAdd(row + c * n * TX, val);
+      if (s.i1 < P)
+        row[c * n * TX] = val;
+      else
+        face[((comp * n + c) * n + s.i2) * K::NE + s.le] = val;
     }
+  }
+}
+
+// The x-face slots of the tile: slot (le + 1) P of row r is the next
+// element's slot 0 (stored by it) plus element le's slot P; past the run's
+// last element (or before an idle one) element le's value alone.  Elements
+// past the mesh contribute nothing.
+template <class K, typename T>
+__device__ __forceinline__ void add_faces(const MeshK<T> &m, const Slab &s, T *tile,
+                                          const T *face) {
+  constexpr int n = K::n, P = K::Dm::P, NE = K::NE, TX = K::TX;
+  const int ex0 = s.x0 / P;
+  for (int k = threadIdx.x; k < 3 * n * n * NE; k += K::NT) {
+    const int le = k % NE, r = k / NE;  // r = (comp n + c) n + b, the tile row
+    if (ex0 + le >= m.nx) continue;
+    T *dst = tile + r * TX + (le + 1) * P;
+    const T f = face[k];
+    if (le + 1 < NE && ex0 + le + 1 < m.nx)
+      *dst += f;
+    else
+      *dst = f;
   }
 }
 
@@ -659,36 +688,33 @@ __device__ __forceinline__ void tile_writeback(const MeshK<T> &m, const Slab &s,
   });
 }
 
-// Transposes of the xi2 and xi1 contractions for the three components,
-// accumulated into the block's tile (zeroed by the caller after the forward
-// pass), then written back to y.  The flux write of component i+1 overlaps
+// Transposes of the xi2 and xi1 contractions for the three components into
+// the block's tile (each element's own slots stored, the shared x-face slots
+// completed by add_faces), then written back to y.  The flux write of component i+1 overlaps
 // the xi1 stage of component i (sg and the st buffers alternate).  sD: the
 // scaled transposed D tables, direction 0 then 1.
 template <class K, typename T, bool GRAD, bool RED>
 __device__ __forceinline__ void transpose_all(const MeshK<T> &m, const Slab &s,
                                               const T (&A)[3][3][K::n], const T *sB, const T *sD,
-                                              T *sg, T *st, T *tile, const int64_t *s_row,
-                                              T *__restrict__ y, bool mask,
+                                              T *sg, T *st, T *tile, T *face,
+                                              const int64_t *s_row, T *__restrict__ y, bool mask,
                                               const T *__restrict__ vdot, double &dot) {
   constexpr int HB = (K::Dm::DBUF >= 2) ? K::Dm::SB1 : 0;
   write_g<K, T, GRAD>(A[0], sg, s);
-  __syncthreads();  // also: the zeroed tile is visible to every element
+  __syncthreads();  // also: the forward pass is done with the tile
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     T *sti = st + (i & 1) * HB;
     stage2t<K, T, GRAD>(sB, sD + K::DTS, sg, sti, s);
     elem_sync<K>();
     if (i < 2) write_g<K, T, GRAD>(A[i + 1], sg, s);
-    stage1t_tile<K, T, GRAD>(s, i, sB, sD, sti, tile);
+    stage1t_tile<K, T, GRAD>(s, i, sB, sD, sti, tile, face);
     if (i < 2) elem_sync<K>();
   }
-  __syncthreads();  // the tile holds every element's contributions
+  __syncthreads();  // every element's slots and faces are in LDS
+  add_faces<K>(m, s, tile, face);
+  __syncthreads();
   tile_writeback<K, T, RED>(m, s, s_row, tile, y, mask, vdot, dot);
-}
-
-template <class K, typename T>
-__device__ __forceinline__ void zero_tile(T *tile) {
-  for (int idx = threadIdx.x; idx < K::TILE; idx += K::NT) tile[idx] = T(0);
 }
 
 template <class K, typename T>
@@ -722,7 +748,8 @@ __device__ __forceinline__ void block_partial_t(double v, Reduce red, double *s_
 #define SDME_SETUP_A                                                            \
   __shared__ __align__(16) T smem[K::SMEM];                                     \
   int64_t *s_row = (int64_t *)smem;                                             \
-  T *tile = smem + K::RW + K::NE * K::SE, *s_tab = tile + K::TILEP;             \
+  T *tile = smem + K::RW + K::NE * K::SE, *s_face = tile + K::TILEP;            \
+  T *s_tab = s_face + K::FACEP;                                                 \
   Slab s = make_slab<K>(m);                                                     \
   T s_tv[stage_table_nit<K>()];                                                 \
   request_stage_tables<K>(m, s_tv);                                             \
@@ -759,7 +786,6 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
   __syncthreads();
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
-  if (OUT) zero_tile<K>(tile);
   T mue = s.valid ? (T)mud : T(0), lae = s.valid ? (T)lad : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
@@ -798,7 +824,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_force(MeshK<T> m, const d
   }
   if (OUT) {
     double dummy = 0;
-    transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_row, R, mask != 0, (const T *)nullptr,
+    transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_face, s_row, R, mask != 0, (const T *)nullptr,
                                      dummy);
   }
 }
@@ -863,7 +889,6 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
   }
   T X[3][3][K::n];
   forward_lds<K, T, true>(sB, sD, tile, st, s, X);
-  zero_tile<K>(tile);
   const T mue = s.valid ? (T)mud : T(0), lae = s.valid ? (T)lad : T(0);
   T w12 = sW[s.i1] * sW[s.i2] * m.detJ;
   T A[3][3][K::n];
@@ -980,7 +1005,7 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     atomicMin(m.flag + 1, s.e);
   }
   double dot = 0;
-  transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_row, y, mask != 0,
+  transpose_all<K, T, true, false>(m, s, A, sBt, sDt, su, st, tile, s_face, s_row, y, mask != 0,
                                    (const T *)nullptr, dot);
   if constexpr (PU && FUSED_PAP) {
     __shared__ double s_red[(K::NT + 63) / 64];
