@@ -1591,19 +1591,13 @@ int launch_tangent_q(const MeshK<T> &m, const double *mu, const double *lam, con
 #define SDME_TAN(REC, MASS, PU)                                                                 \
   hipLaunchKernelGGL((k_tangent<P, Q, T, REC, MASS, PU>), grid, block, 0, st, m, mu, lam, ulin, \
                      state, msr, v, y, mask, u, skip)
-  // Stored-state operator (without the fused update) in FP32 at P <= 4: the
-  // instantiation with the mass term runs also without a shift (msr = 0 adds
-  // exact zeros), as it is compiled to faster code there (7-12 % at ~2e7 DOF,
-  // P = 2 and 4; equal or slower at P = 6, 8, in FP64 and for the fused PCG
-  // operator).
-  const bool mass_code = mass || (sizeof(T) == 4 && P <= 4);
   if (ulin) {
     if (pu) return -2;  // the fused update is provided for the stored-state operator
     if (mass) SDME_TAN(true, true, false); else SDME_TAN(true, false, false);
   } else if (pu) {
     if (mass) SDME_TAN(false, true, true); else SDME_TAN(false, false, true);
   } else {
-    if (mass_code) SDME_TAN(false, true, false); else SDME_TAN(false, false, false);
+    if (mass) SDME_TAN(false, true, false); else SDME_TAN(false, false, false);
   }
 #undef SDME_TAN
   if (m.stage && launch_stage_gather<T>(P, m, K::NE, K::TX, K::TILE, mask, y, skip, st)) return -1;
