@@ -45,11 +45,16 @@ struct EK {
   // stage1t_tile)
   static constexpr int FACEW = 3 * n * n * NE, FACEP = Dm::rup(FACEW);
   static constexpr int SMEM = RW + NE * SE + TILEP + FACEP + TSX;
-  // Stored-state tangent action: PIPE selects two named buffers of
-  // Gauss-point slabs requested ahead (the first two before the forward
+  // Stored-state tangent action: PIPE selects DEPTH named buffers of
+  // Gauss-point slabs requested ahead (the first DEPTH before the forward
   // contractions); otherwise one slab is prefetched per step.  Chosen by
-  // measurement at ~2e7 DOF per order and precision (FP32, P >= 4).
+  // measurement at ~2e7 DOF per order and precision (FP32, P >= 4); three
+  // buffers where they keep the kernel within 256 VGPRs (P <= 6), two above.
+#ifndef SDME_PIPE3
+#define SDME_PIPE3 1
+#endif
   static constexpr bool PIPE = sizeof(T) == 4 && P >= 4;
+  static constexpr int DEPTH = (SDME_PIPE3 && P <= 6) ? 3 : 2;
   // every element's Q^2 threads lie in one wave (Q^2 divides the wave size):
   // the element-private LDS exchanges of the contraction stages then need
   // only a wave-level synchronisation
@@ -872,12 +877,13 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     gather_tile<K>(m, s, s_row, v, mask != 0, tile);
     __syncthreads();
   }
-  // two named buffers: the first two slabs are requested once the gather has
+  // named buffers: the first DEPTH slabs are requested once the gather has
   // completed (memory waits are in order, so earlier requests would be
   // waited for by the gather) and stay in flight through the forward
   // contractions, which wait only on LDS; the empty asm keeps the compiler
   // from moving the loads down to their first use.
-  T Ga[10], Gc[10];
+  constexpr int DEPTH = K::DEPTH;
+  T Ga[10], Gc[10], Gb[10];
   if (PIPE) {
 #pragma unroll
     for (int k = 0; k < 10; k++) Ga[k] = sp[k * QQQ];
@@ -885,6 +891,12 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
     const int o1 = min(1, Q - 1) * K::QQ;
 #pragma unroll
     for (int k = 0; k < 10; k++) Gc[k] = sp[k * QQQ + o1];
+    if constexpr (DEPTH == 3) {
+      __builtin_amdgcn_sched_barrier(0);
+      const int o2 = min(2, Q - 1) * K::QQ;
+#pragma unroll
+      for (int k = 0; k < 10; k++) Gb[k] = sp[k * QQQ + o2];
+    }
     asm volatile("" ::: "memory");
   }
   T X[3][3][K::n];
@@ -965,25 +977,34 @@ __global__ __launch_bounds__((EK<P, Q, T>::NT)) void k_tangent(
       point(q3, kk.G, mue - lae * kk.lnJ);
     }
   } else if (PIPE) {
-    // Gauss-point slabs in pairs with the two named buffers (no register
-    // rotation): slab q3 + 2 is requested into a buffer as soon as slab q3
-    // has used it, and each wait leaves the other buffer's requests
-    // outstanding.  The last requests repeat the last slab so that every
-    // request is unconditional; the scheduling barriers keep each request
-    // after the computation that frees its buffer.
+    // Gauss-point slabs in groups of DEPTH with the named buffers (no
+    // register rotation): slab q3 + DEPTH is requested into a buffer as soon
+    // as slab q3 has used it, and each wait leaves the other buffers'
+    // requests outstanding.  Requests past the column repeat its last slab
+    // (min(., Q - 1)) so that every request is unconditional; the scheduling
+    // barriers keep each request after the computation that frees its buffer.
 #pragma unroll 1
-    for (int q3 = 0; q3 < Q; q3 += 2) {
+    for (int q3 = 0; q3 < Q; q3 += DEPTH) {
       point(q3, Ga, Ga[9]);
       __builtin_amdgcn_sched_barrier(0);
-      const int oa = min(q3 + 2, Q - 1) * K::QQ;
+      const int oa = min(q3 + DEPTH, Q - 1) * K::QQ;
 #pragma unroll
       for (int k = 0; k < 10; k++) Ga[k] = sp[k * QQQ + oa];
-      if (Q % 2 == 0 || q3 + 1 < Q) {
+      if (Q % DEPTH == 0 || q3 + 1 < Q) {
         point(q3 + 1, Gc, Gc[9]);
         __builtin_amdgcn_sched_barrier(0);
-        const int oc = min(q3 + 3, Q - 1) * K::QQ;
+        const int oc = min(q3 + 1 + DEPTH, Q - 1) * K::QQ;
 #pragma unroll
         for (int k = 0; k < 10; k++) Gc[k] = sp[k * QQQ + oc];
+      }
+      if constexpr (DEPTH == 3) {
+        if (Q % 3 == 0 || q3 + 2 < Q) {
+          point(q3 + 2, Gb, Gb[9]);
+          __builtin_amdgcn_sched_barrier(0);
+          const int ob = min(q3 + 2 + DEPTH, Q - 1) * K::QQ;
+#pragma unroll
+          for (int k = 0; k < 10; k++) Gb[k] = sp[k * QQQ + ob];
+        }
       }
     }
   } else {

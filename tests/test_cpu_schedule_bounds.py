@@ -8,30 +8,46 @@ each Gauss point).  Thread t of a block serves element slab le = t / Q^2 and
 Gauss-point column t2 = t mod Q^2; its slab pointer is
   sp = (valid ? e : 0) * 10 Q^3 + t2
 and Gauss-point slab j of word k is read at sp + k Q^3 + j Q^2.  The model
-enumerates the slabs each schedule requests -- the kept ones (two named
-buffers stepping q3 by two with the clamp min(q3 + 2, Q - 1), and the
-one-slab prefetch guarded by q3 + 1 < Q) and the unclamped variants of the
+enumerates the slabs each schedule requests -- the kept ones (DEPTH = 2 or 3
+named buffers stepping q3 by DEPTH with the clamp min(q3 + DEPTH, Q - 1), and
+the one-slab prefetch guarded by q3 + 1 < Q) and the unclamped variants of the
 same schedules -- for P = 1..8, Q in {P+1, P+2}, every run length NE a block
 can have, meshes with ragged last blocks and idle element slabs.  The
 unclamped variants request slab Q (one buffer) or slabs Q, Q + 1 (two
 buffers) in their last step and read past the element's block; for the last
 element of the mesh that is past the end of the caller's state buffer, a
 fault whenever the allocation ends at a page boundary.  The tile gather is
-modelled the same way against [0, 3 Nn)."""
+modelled the same way against [0, 3 Nn).  A last check follows the buffers
+through the pipelined loop: each point reads the slab of its own index."""
 import itertools
 
 import pytest
 
 
-def slabs_pipe(Q, clamp=True):
-    """Slabs requested by the two-buffer schedule, in order."""
+def slabs_pipe(Q, clamp=True, depth=2):
+    """Slabs requested by the schedule with `depth` named buffers, in order,
+    and the slab each point of the loop consumes (buffer contents at use)."""
     cl = (lambda j: min(j, Q - 1)) if clamp else (lambda j: j)
-    req = [0, cl(1)]                       # both buffers before the forward pass
-    for q3 in range(0, Q, 2):
-        req.append(cl(q3 + 2))             # buffer a, after slab q3 is used
-        if Q % 2 == 0 or q3 + 1 < Q:
-            req.append(cl(q3 + 3))         # buffer c, after slab q3 + 1 is used
+    req = [cl(j) for j in range(depth)]    # every buffer before the forward pass
+    for q3 in range(0, Q, depth):
+        for b in range(depth):
+            if b == 0 or Q % depth == 0 or q3 + b < Q:
+                req.append(cl(q3 + b + depth))  # buffer b, after slab q3 + b is used
     return req
+
+
+def pipe_uses(Q, depth):
+    """(point, slab held by its buffer) for every point of the pipelined loop:
+    buffer b holds the slab requested last into it."""
+    cl = lambda j: min(j, Q - 1)
+    held = [cl(j) for j in range(depth)]
+    uses = []
+    for q3 in range(0, Q, depth):
+        for b in range(depth):
+            if b == 0 or Q % depth == 0 or q3 + b < Q:
+                uses.append((q3 + b, held[b]))
+                held[b] = cl(q3 + b + depth)
+    return uses
 
 
 def slabs_one(Q, guard=True):
@@ -100,14 +116,14 @@ ORDERS = [(P, Q) for P in range(1, 9) for Q in (P + 1, P + 2)]
 @pytest.mark.parametrize("P,Q", ORDERS, ids=["P%dQ%d" % pq for pq in ORDERS])
 def test_kept_state_schedules_stay_in_bounds(P, Q):
     QQ = Q * Q
-    pipe, one = slabs_pipe(Q), slabs_one(Q)
-    assert slab_consumed(Q, pipe) and slab_consumed(Q, one)
-    assert max(pipe) == Q - 1 and max(one) == Q - 1
+    pipe, pipe3, one = slabs_pipe(Q), slabs_pipe(Q, depth=3), slabs_one(Q)
+    assert slab_consumed(Q, pipe) and slab_consumed(Q, pipe3) and slab_consumed(Q, one)
+    assert max(pipe) == Q - 1 and max(pipe3) == Q - 1 and max(one) == Q - 1
     for NE in range(1, max(1, 256 // QQ) + 1):
         # rows shorter, equal and longer than a block, with a ragged tail
         for nx, ny, nz in ((1, 1, 1), (NE, 1, 2), (NE + 1, 2, 1), (2 * NE + 3, 1, 1)):
             E = nx * ny * nz
-            for slabs in (pipe, one):
+            for slabs in (pipe, pipe3, one):
                 lo, hi = state_addresses(P, Q, NE, nx, ny, nz, slabs)
                 assert lo >= 0 and hi < E * 10 * Q ** 3, (P, Q, NE, nx, ny, nz)
 
@@ -139,3 +155,14 @@ def test_tile_gather_stays_in_bounds(P):
             for nx, ny, nz in ((1, 1, 1), (NE + 1, 2, 1), (2 * NE + 1, 1, 2)):
                 lo, hi, end = gather_addresses(P, NE, nx, ny, nz)
                 assert lo >= 0 and hi < end
+
+
+@pytest.mark.parametrize("depth", (2, 3))
+@pytest.mark.parametrize("Q", range(2, 11))
+def test_pipelined_points_read_their_own_slab(Q, depth):
+    # every point q3 = 0..Q-1 runs exactly once, in order, and its buffer then
+    # holds slab q3 (the clamp only repeats the last slab in requests that no
+    # point consumes)
+    uses = pipe_uses(Q, depth)
+    assert [q for q, _ in uses] == list(range(Q))
+    assert all(q == slab for q, slab in uses)
