@@ -108,20 +108,24 @@ def test_tangent_masked(pair):
     assert relerr(pair.host(y), ref) < TOL64
 
 
-def test_tangent_fp32(pair):
+@pytest.mark.parametrize("shift", [0.0, 40.0])
+def test_tangent_fp32(pair, shift):
+    # shift 0 runs the plain instantiation, 40 the one with the mass term
+    # (both with the state pipeline of the order: one, two or three slabs
+    # ahead, Q a multiple of three or not)
     u, v = _inputs(pair, 5)
     f32 = pair.torch.float32
     u32, v32 = u.astype(np.float32), v.astype(np.float32)
     st = pair.empty_state(f32)
     pair.ctx.linearize(pair.mat, FP32, pair.dev(u32, f32), st)
     ref = pair.pb.mesh.tangent_apply(pair.pb.mu, pair.pb.lam, u32.astype(np.float64),
-                                     v32.astype(np.float64), 40.0 * pair.rho)
+                                     v32.astype(np.float64), shift * pair.rho)
     y = pair.zeros(f32)
-    pair.ctx.tangent_apply(pair.mat, FP32, pair.dev(v32, f32), y, state=st, mass_shift=40.0)
+    pair.ctx.tangent_apply(pair.mat, FP32, pair.dev(v32, f32), y, state=st, mass_shift=shift)
     assert relerr(pair.host(y), ref) < TOL32
     y2 = pair.zeros(f32)
     pair.ctx.tangent_apply(pair.mat, FP32, pair.dev(v32, f32), y2, u_lin=pair.dev(u32, f32),
-                           mass_shift=40.0)
+                           mass_shift=shift)
     assert relerr(pair.host(y2), ref) < TOL32
 
 

@@ -60,6 +60,42 @@ def test_pcg_mixed_precision_reaches_fp64_tolerance(cube8):
     assert relerr(xg, xr) < 1e-8
 
 
+# Orders whose Gauss-point count Q is not a multiple of three (the FP32 PCG
+# operator's state pipeline then ends on a partial group) and a case where it
+# is; rows span several element blocks with a ragged last block.
+FUSED_CASES = [
+    ((13, 2, 1), 4, ob.SDME_H, 5),
+    ((7, 2, 1), 5, ob.NODAL, None),
+    ((5, 2, 1), 6, ob.SDME_K, None),
+    ((7, 1, 2), 6, ob.NODAL, 7),
+    ((11, 2, 1), 4, ob.SDME_M, None),
+]
+
+
+@pytest.mark.parametrize("shift", [0.0, 4.0])
+@pytest.mark.parametrize("n,P,kind,Q", FUSED_CASES,
+                         ids=["P%d-Q%d" % (c[1], c[3] or c[1] + 2) for c in FUSED_CASES])
+def test_mixed_pcg_fused_operator_two_iterations(n, P, kind, Q, shift):
+    # Two mixed-precision PCG iterations from x = 0 run the FP32 operator with
+    # the fused direction update twice; x2 = a0 z0 + a1 (z1 + b0 z0) depends on
+    # every entry of the first operator output.  The oracle runs the same two
+    # FP64 CG iterations (direct element loops).
+    p = Pair(n, (1.0, 0.4, 0.3), P, kind=kind, Q=Q, rho=1.1,
+             dirichlet=inputs.face_bits(0) | inputs.face_bits(3))
+    G = np.zeros((3, 3))
+    G[0, 0] = -0.05
+    u = p.ctx.affine_field([0, 0, 0], G) + p.mask * p.rand(31, 1e-3)
+    b = p.mask * inputs.uniform(32, p.N, -1, 1)
+    x = p.zeros()
+    st = p.ctx.jacobi_pcg(p.mat, FP32, p.dev(b), x, u_lin=p.dev(u), mass_shift=shift, rtol=1e-30,
+                          maxit=2, inner_rtol=1e-30, check=False)
+    assert st["iterations"] == 2
+    cm = shift * p.rho
+    xr, its, _ = osv.pcg(p.pb.A(u, cm), b, p.pb.diag(u, cm), 1e-30, 2)
+    assert its == 2
+    assert relerr(p.host(x), xr) < 1e-5
+
+
 def test_pcg_with_mass_shift_and_mass_only(cube8):
     p = cube8
     u = p.mask * p.rand(5, 1e-3)
