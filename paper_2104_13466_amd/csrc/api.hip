@@ -240,7 +240,8 @@ int do_replace(sdme_ctx *c, const sdme_material *mat, Replace &rep, float *x32, 
 // Jacobi PCG in precision T on vectors of type T: b masked on input, x out.
 // The operator's p^T A p comes from a separate streaming dot product.  With
 // a second direction buffer p2 and the stored-state operator, the update
-// p = z + beta p is fused into the operator's gather (p and p2 alternate).
+// p = z + beta p is fused into the operator's gather (p and p2 alternate),
+// and x is updated every other iteration with both directions.
 template <typename T>
 int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b, T *x, const T *d,
              double rtol, int maxit, T *r, T *p, T *Ap, int slot, int *iters, double *rel,
@@ -268,6 +269,10 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
     // launched iterations past a stop return at once, so the direction
     // buffers alternate with the iterations that ran
     if (fused) par = c->h_pcg[slot].iters & 1;
+    // complete a deferred x update (pb[par] is the last direction) before a
+    // residual replacement reads x, at the end, and at every chunk boundary
+    if (c->h_pcg[slot].xpend && launch_pcg_xflush<T>(x, pb[par], s, N, st))
+      return SDME_EDEVICE;
     if constexpr (sizeof(T) == 4) {
       if (rep && (done == 5 || done == 1)) {
         // the FP32 residual met the replacement or the stop threshold: replace
@@ -304,7 +309,11 @@ int pcg_core(sdme_ctx *c, const sdme_material *mat, const Op<T> &op, const T *b,
       } else if (launch_pcg_pap<T>(pc, Ap, s, N, red_at(c, 6), st)) {
         return SDME_EDEVICE;
       }
-      if (launch_pcg_update<T>(x, r, pc, Ap, d, s, N, red_at(c, 4), st)) return SDME_EDEVICE;
+      // fused: pb[par ^ 1] still holds the previous direction (the next
+      // operator overwrites it), so the x update can lag one iteration
+      if (launch_pcg_update<T>(x, r, pc, Ap, d, s, N, red_at(c, 4), st,
+                               fused ? (const T *)pb[par ^ 1] : nullptr))
+        return SDME_EDEVICE;
       if (!fused && launch_pcg_pupdate<T>(pc, r, d, s, N, st)) return SDME_EDEVICE;
     }
     if (c->prof) {

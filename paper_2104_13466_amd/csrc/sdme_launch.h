@@ -103,11 +103,12 @@ struct PcgDev {
   double rz, pAp, rznew, rr, tol2, bb, alpha, beta;
   double upd2;   // residual-replacement threshold (mixed precision); 0 = off
   double rz_old; // r.z before the last update (for beta after a replacement)
+  double alpha_pend;  // step length of the direction whose x update is pending
   int done;  // 0 running, 1 converged, 2 breakdown, 3 non-finite, 4 iteration limit,
              // 5 residual replacement requested
   int iters;
   int maxit;
-  int pad;
+  int xpend;  // 1: x lacks alpha_pend times the previous direction (deferred update)
 };
 
 constexpr int VEC_BLOCKS = 4096;
@@ -137,7 +138,10 @@ int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int ma
                     int64_t n, Reduce red2, hipStream_t st);
 template <typename T>
 int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int64_t n,
-                      Reduce red2, hipStream_t st);
+                      Reduce red2, hipStream_t st, const T *p_prev = nullptr);
+// x += alpha_pend p (the update deferred by launch_pcg_update), xpend = 0
+template <typename T>
+int launch_pcg_xflush(T *x, const T *p, PcgDev *s, int64_t n, hipStream_t st);
 template <typename T>
 int launch_pcg_pupdate(T *p, const T *r, const T *d, const PcgDev *s, int64_t n, hipStream_t st);
 // pAp = p . Ap (skipped when done)

@@ -216,6 +216,8 @@ __global__ __launch_bounds__(NTF) void k_pcg_init_fin(PcgDev *s, double rtol, in
     s->maxit = maxit;
     s->pAp = 0;
     s->beta = 0;
+    s->alpha_pend = 0;
+    s->xpend = 0;
     s->done = (rr <= s->tol2) ? 1 : (std::isfinite(rr) ? 0 : 3);
   }
 }
@@ -309,23 +311,40 @@ int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, 
 
 // update: alpha = rz / pAp; x += alpha p; r -= alpha Ap; Ap = 0;
 // rznew = r.(d r); rr = r.r; then beta = rznew / rz, convergence test.
+// With the previous direction p_prev (the fused operator keeps p_k and p_k-1
+// in two buffers) the x update is done every other iteration: a step with
+// xpend = 0 leaves x alone (alpha is kept as alpha_pend), the next one adds
+// alpha_pend p_prev + alpha p, so two iterations read x once instead of twice
+// (16 instead of 24 bytes per FP32 DOF); launch_pcg_xflush completes x.
 template <typename T>
 __global__ __launch_bounds__(NTV) void k_pcg_update(T *__restrict__ x, T *__restrict__ r,
                                                     const T *__restrict__ p, T *__restrict__ Ap,
                                                     const T *__restrict__ d, PcgDev *s, int64_t n,
-                                                    Reduce red) {
+                                                    Reduce red, const T *__restrict__ p_prev) {
   __shared__ double s_red[NTV / 64];
   if (s->done) return;
   double pAp = s->pAp;
   double alpha_d = (pAp > 0.0) ? s->rz / pAp : 0.0;
   T alpha = (T)alpha_d;
   double a = 0, b = 0;
-  SDME_VLOOP(T pi = p[i]; T api = Ap[i]; T xi = x[i]; T ri = r[i]; T di = d[i];
-             x[i] = xi + alpha * pi; ri = ri - alpha * api; r[i] = ri; Ap[i] = T(0);
-             T z = ri * di; a += (double)ri * (double)z; b += (double)ri * (double)ri;)
+  if (!p_prev) {
+    SDME_VLOOP(T pi = p[i]; T api = Ap[i]; T xi = x[i]; T ri = r[i]; T di = d[i];
+               x[i] = xi + alpha * pi; ri = ri - alpha * api; r[i] = ri; Ap[i] = T(0);
+               T z = ri * di; a += (double)ri * (double)z; b += (double)ri * (double)ri;)
+  } else if (!s->xpend) {
+    SDME_VLOOP(T api = Ap[i]; T ri = r[i]; T di = d[i];
+               ri = ri - alpha * api; r[i] = ri; Ap[i] = T(0);
+               T z = ri * di; a += (double)ri * (double)z; b += (double)ri * (double)ri;)
+  } else {
+    const T alpha0 = (T)s->alpha_pend;
+    SDME_VLOOP(T p0 = p_prev[i]; T pi = p[i]; T api = Ap[i]; T xi = x[i]; T ri = r[i];
+               T di = d[i]; x[i] = xi + (alpha0 * p0 + alpha * pi); ri = ri - alpha * api;
+               r[i] = ri; Ap[i] = T(0); T z = ri * di; a += (double)ri * (double)z;
+               b += (double)ri * (double)ri;)
+  }
   block_partials2(a, b, red, s_red);
 }
-__global__ __launch_bounds__(NTF) void k_pcg_update_fin(PcgDev *s, Reduce red, int nb) {
+__global__ __launch_bounds__(NTF) void k_pcg_update_fin(PcgDev *s, Reduce red, int nb, int defer) {
   __shared__ double s_red[NTF / 64];
   if (s->done) return;
   double rznew, rr;
@@ -333,6 +352,14 @@ __global__ __launch_bounds__(NTF) void k_pcg_update_fin(PcgDev *s, Reduce red, i
   if (threadIdx.x == 0) {
     double pAp = s->pAp;
     s->alpha = (pAp > 0.0) ? s->rz / pAp : 0.0;
+    if (defer) {
+      if (s->xpend) {
+        s->xpend = 0;
+      } else {
+        s->xpend = 1;
+        s->alpha_pend = s->alpha;
+      }
+    }
     s->beta = rznew / s->rz;
     s->rz_old = s->rz;
     s->rz = rznew;
@@ -347,10 +374,27 @@ __global__ __launch_bounds__(NTF) void k_pcg_update_fin(PcgDev *s, Reduce red, i
 }
 template <typename T>
 int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int64_t n,
-                      Reduce red2, hipStream_t st) {
+                      Reduce red2, hipStream_t st, const T *p_prev) {
   const int nb = grid_for_u(n);
-  hipLaunchKernelGGL(k_pcg_update<T>, dim3(nb), dim3(NTV), 0, st, x, r, p, Ap, d, s, n, red2);
-  hipLaunchKernelGGL(k_pcg_update_fin, dim3(1), dim3(NTF), 0, st, s, red2, nb);
+  hipLaunchKernelGGL(k_pcg_update<T>, dim3(nb), dim3(NTV), 0, st, x, r, p, Ap, d, s, n, red2,
+                     p_prev);
+  hipLaunchKernelGGL(k_pcg_update_fin, dim3(1), dim3(NTF), 0, st, s, red2, nb,
+                     p_prev ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// The pending half of a deferred x update (launched by the host when it has
+// read xpend = 1; no other block reads xpend, so block 0 clears it).
+template <typename T>
+__global__ __launch_bounds__(NTV) void k_pcg_xflush(T *__restrict__ x, const T *__restrict__ p,
+                                                    PcgDev *s, int64_t n) {
+  const T a = (T)s->alpha_pend;
+  SDME_VLOOP(x[i] += a * p[i];)
+  if (blockIdx.x == 0 && threadIdx.x == 0) s->xpend = 0;
+}
+template <typename T>
+int launch_pcg_xflush(T *x, const T *p, PcgDev *s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_xflush<T>, dim3(grid_for_u(n)), dim3(NTV), 0, st, x, p, s, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -508,9 +552,12 @@ template int launch_pcg_init<double>(const double *, const double *, double *, P
 template int launch_pcg_init<float>(const float *, const float *, float *, PcgDev *, double, int,
                                     double, int64_t, Reduce, hipStream_t);
 template int launch_pcg_update<double>(double *, double *, const double *, double *,
-                                       const double *, PcgDev *, int64_t, Reduce, hipStream_t);
+                                       const double *, PcgDev *, int64_t, Reduce, hipStream_t,
+                                       const double *);
 template int launch_pcg_update<float>(float *, float *, const float *, float *, const float *,
-                                      PcgDev *, int64_t, Reduce, hipStream_t);
+                                      PcgDev *, int64_t, Reduce, hipStream_t, const float *);
+template int launch_pcg_xflush<double>(double *, const double *, PcgDev *, int64_t, hipStream_t);
+template int launch_pcg_xflush<float>(float *, const float *, PcgDev *, int64_t, hipStream_t);
 template int launch_pcg_pupdate<double>(double *, const double *, const double *, const PcgDev *,
                                         int64_t, hipStream_t);
 template int launch_pcg_pap<double>(const double *, const double *, PcgDev *, int64_t, Reduce,
