@@ -96,6 +96,28 @@ def test_mixed_pcg_fused_operator_two_iterations(n, P, kind, Q, shift):
     assert relerr(p.host(x), xr) < 1e-5
 
 
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["mixed", "fp64"])
+@pytest.mark.parametrize("its", [1, 3])
+@pytest.mark.parametrize("n,P,kind,Q", [FUSED_CASES[0], FUSED_CASES[1]], ids=["P4-Q5", "P5-Q7"])
+def test_pcg_stopping_with_a_pending_x_update(n, P, kind, Q, its, prec):
+    # With the fused direction update x is updated every other iteration;
+    # stopping after an odd count leaves half an update pending, which the
+    # solver completes before it returns.  x after `its` iterations from 0
+    # against the same FP64 CG iterations of the oracle.
+    p = Pair(n, (1.0, 0.4, 0.3), P, kind=kind, Q=Q, rho=1.1,
+             dirichlet=inputs.face_bits(0) | inputs.face_bits(3))
+    u = p.mask * p.rand(33, 1e-3)
+    b = p.mask * inputs.uniform(34, p.N, -1, 1)
+    x = p.zeros()
+    st = p.ctx.jacobi_pcg(p.mat, prec, p.dev(b), x, u_lin=p.dev(u), mass_shift=4.0, rtol=1e-30,
+                          maxit=its, inner_rtol=1e-30, check=False)
+    assert st["iterations"] == its
+    cm = 4.0 * p.rho
+    xr, k, _ = osv.pcg(p.pb.A(u, cm), b, p.pb.diag(u, cm), 1e-30, its)
+    assert k == its
+    assert relerr(p.host(x), xr) < (1e-5 if prec == FP32 else 1e-11)
+
+
 def test_pcg_with_mass_shift_and_mass_only(cube8):
     p = cube8
     u = p.mask * p.rand(5, 1e-3)
