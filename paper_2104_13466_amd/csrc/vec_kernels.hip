@@ -1,6 +1,6 @@
 // Vector, reduction and face kernels of libsdme: fused PCG updates with
-// deterministic FP64 reductions (wave shuffles, one partial per block, the
-// last block sums the partials in block order), conversions, Dirichlet
+// deterministic FP64 reductions (wave shuffles, one partial per block, a
+// one-block kernel sums the partials in a fixed order), conversions, Dirichlet
 // masking, and the surface terms (dead traction, rigid-plane penalty).
 #include <hip/hip_runtime.h>
 
@@ -28,21 +28,24 @@ __device__ __forceinline__ void block_partials2(double a, double b, Reduce red, 
   }
 }
 
-// Sums of the partials of nb blocks in a fixed order (one block of NTF
-// threads: thread t adds partials t, t + NTF, ... in turn, then the block sum
+// Sums of the partials of nb blocks in a fixed order (one block of NT
+// threads: thread t adds partials t, t + NT, ... in turn, then the block sum
 // adds the threads' sums in thread order); valid in thread 0.  The finishing
-// kernels run alone on the device and wait on memory: a wide block with UF
-// independent loads per thread in flight keeps them short (the pairs of
-// element-kernel partials reach ~1.5e4 at 2e7 DOF).
-constexpr int NTF = 1024, UF = 4;
+// kernels run alone on the device and wait on memory: with many partials
+// (~4e3 from the streaming kernels, ~1.5e4 from the FP64 fused operator at
+// 2e7 DOF) a wide block with UF independent loads per thread in flight keeps
+// them short; with few (small meshes) the narrow block's shorter block sum
+// is faster.
+constexpr int NTF = 1024, UF = 4, FIN_WIDE_MIN = 1024;
+template <int NT>
 __device__ __forceinline__ void sum_partials2(const double *partials, int nb, double &a, double &b,
                                               double *s_red) {
   double pa = 0, pb = 0;
-  for (int i0 = threadIdx.x; i0 < nb; i0 += UF * NTF) {
+  for (int i0 = threadIdx.x; i0 < nb; i0 += UF * NT) {
     double xa[UF], xb[UF];
 #pragma unroll
     for (int u = 0; u < UF; u++) {
-      const int i = i0 + u * NTF;
+      const int i = i0 + u * NT;
       xa[u] = i < nb ? partials[2 * i] : 0.0;
       xb[u] = i < nb ? partials[2 * i + 1] : 0.0;
     }
@@ -52,9 +55,17 @@ __device__ __forceinline__ void sum_partials2(const double *partials, int nb, do
       pb += xb[u];
     }
   }
-  a = block_sum<NTF>(pa, s_red);
-  b = block_sum<NTF>(pb, s_red);
+  a = block_sum<NT>(pa, s_red);
+  b = block_sum<NT>(pb, s_red);
 }
+// One-block finishing kernel K<NT> over nb partials, NT = NTF or NTV by nb.
+#define SDME_FIN(K, nb, st, ...)                                                   \
+  do {                                                                            \
+    if ((nb) > FIN_WIDE_MIN)                                                      \
+      hipLaunchKernelGGL(K<NTF>, dim3(1), dim3(NTF), 0, st, __VA_ARGS__);         \
+    else                                                                          \
+      hipLaunchKernelGGL(K<NTV>, dim3(1), dim3(NTV), 0, st, __VA_ARGS__);         \
+  } while (0)
 
 static int grid_for(int64_t n) {
   int64_t b = (n + NTV - 1) / NTV;
@@ -171,10 +182,11 @@ __global__ __launch_bounds__(NTV) void k_dot2(const T *__restrict__ x, const T *
   SDME_VLOOP(double xv = (double)x[i]; double yv = (double)y[i]; a += xv * yv; b += yv * yv;)
   block_partials2(a, b, red, s_red);
 }
-__global__ __launch_bounds__(NTF) void k_fin2(Reduce red, int nb) {
-  __shared__ double s_red[NTF / 64];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fin2(Reduce red, int nb) {
+  __shared__ double s_red[NT / 64];
   double a, b;
-  sum_partials2(red.partials, nb, a, b, s_red);
+  sum_partials2<NT>(red.partials, nb, a, b, s_red);
   if (threadIdx.x == 0) {
     red.result[0] = a;
     red.result[1] = b;
@@ -184,7 +196,7 @@ template <typename T>
 int launch_dot2(const T *x, const T *y, int64_t n, Reduce red2, hipStream_t st) {
   const int nb = grid_for_u(n);
   hipLaunchKernelGGL(k_dot2<T>, dim3(nb), dim3(NTV), 0, st, x, y, n, red2);
-  hipLaunchKernelGGL(k_fin2, dim3(1), dim3(NTF), 0, st, red2, nb);
+  SDME_FIN(k_fin2, nb, st, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -200,11 +212,12 @@ __global__ __launch_bounds__(NTV) void k_pcg_init(const T *__restrict__ r, const
              b += (double)ri * (double)ri;)
   block_partials2(a, b, red, s_red);
 }
-__global__ __launch_bounds__(NTF) void k_pcg_init_fin(PcgDev *s, double rtol, int maxit,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pcg_init_fin(PcgDev *s, double rtol, int maxit,
                                                       double delta, Reduce red, int nb) {
-  __shared__ double s_red[NTF / 64];
+  __shared__ double s_red[NT / 64];
   double rz, rr;
-  sum_partials2(red.partials, nb, rz, rr, s_red);
+  sum_partials2<NT>(red.partials, nb, rz, rr, s_red);
   if (threadIdx.x == 0) {
     s->rz = rz;
     s->rr = rr;
@@ -226,7 +239,7 @@ int launch_pcg_init(const T *r, const T *d, T *p, PcgDev *s, double rtol, int ma
                     int64_t n, Reduce red2, hipStream_t st) {
   const int nb = grid_for_u(n);
   hipLaunchKernelGGL(k_pcg_init<T>, dim3(nb), dim3(NTV), 0, st, r, d, p, n, red2);
-  hipLaunchKernelGGL(k_pcg_init_fin, dim3(1), dim3(NTF), 0, st, s, rtol, maxit, delta, red2, nb);
+  SDME_FIN(k_pcg_init_fin, nb, st, s, rtol, maxit, delta, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -239,21 +252,22 @@ __global__ __launch_bounds__(NTV) void k_pcg_pap(const T *__restrict__ p, const 
   SDME_VLOOP(a += (double)p[i] * (double)Ap[i];)
   block_partials2(a, 0.0, red, s_red);
 }
-__global__ __launch_bounds__(NTF) void k_pcg_pap_fin(PcgDev *s, Reduce red, int nb) {
-  __shared__ double s_red[NTF / 64];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pcg_pap_fin(PcgDev *s, Reduce red, int nb) {
+  __shared__ double s_red[NT / 64];
   if (s->done) return;
   double a, b;
-  sum_partials2(red.partials, nb, a, b, s_red);
+  sum_partials2<NT>(red.partials, nb, a, b, s_red);
   if (threadIdx.x == 0) s->pAp = a;
 }
 // Finishing passes for reductions whose block partials were written by an
 // element kernel of nb blocks.
 int launch_fin2(Reduce red2, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin2, dim3(1), dim3(NTF), 0, st, red2, nb);
+  SDME_FIN(k_fin2, nb, st, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 int launch_pcg_pap_fin(PcgDev *s, Reduce red2, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_pap_fin, dim3(1), dim3(NTF), 0, st, s, red2, nb);
+  SDME_FIN(k_pcg_pap_fin, nb, st, s, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -261,7 +275,7 @@ template <typename T>
 int launch_pcg_pap(const T *p, const T *Ap, PcgDev *s, int64_t n, Reduce red2, hipStream_t st) {
   const int nb = grid_for_u(n);
   hipLaunchKernelGGL(k_pcg_pap<T>, dim3(nb), dim3(NTV), 0, st, p, Ap, s, n, red2);
-  hipLaunchKernelGGL(k_pcg_pap_fin, dim3(1), dim3(NTF), 0, st, s, red2, nb);
+  SDME_FIN(k_pcg_pap_fin, nb, st, s, red2, nb);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -278,11 +292,12 @@ __global__ __launch_bounds__(NTV) void k_pcg_replace(float *__restrict__ r32,
              a += (double)rf * (double)(rf * d[i]); b += rv * rv;)
   block_partials2(a, b, red, s_red);
 }
-__global__ __launch_bounds__(NTF) void k_pcg_replace_fin(PcgDev *s, double delta, Reduce red,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pcg_replace_fin(PcgDev *s, double delta, Reduce red,
                                                          int nb) {
-  __shared__ double s_red[NTF / 64];
+  __shared__ double s_red[NT / 64];
   double rz, rr;
-  sum_partials2(red.partials, nb, rz, rr, s_red);
+  sum_partials2<NT>(red.partials, nb, rz, rr, s_red);
   if (threadIdx.x == 0) {
     s->beta = rz / s->rz_old;
     s->rz = rz;
@@ -303,7 +318,7 @@ int launch_pcg_replace(float *r32, const double *r64, const float *d, float *p, 
                        double delta, int64_t n, Reduce red2, bool update_p, hipStream_t st) {
   const int nb = grid_for_u(n);
   hipLaunchKernelGGL(k_pcg_replace, dim3(nb), dim3(NTV), 0, st, r32, r64, d, n, red2);
-  hipLaunchKernelGGL(k_pcg_replace_fin, dim3(1), dim3(NTF), 0, st, s, delta, red2, nb);
+  SDME_FIN(k_pcg_replace_fin, nb, st, s, delta, red2, nb);
   if (update_p)
     hipLaunchKernelGGL(k_pcg_pupdate_force, dim3(grid_for(n)), dim3(NTV), 0, st, p, r32, d, s, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -344,11 +359,12 @@ __global__ __launch_bounds__(NTV) void k_pcg_update(T *__restrict__ x, T *__rest
   }
   block_partials2(a, b, red, s_red);
 }
-__global__ __launch_bounds__(NTF) void k_pcg_update_fin(PcgDev *s, Reduce red, int nb, int defer) {
-  __shared__ double s_red[NTF / 64];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pcg_update_fin(PcgDev *s, Reduce red, int nb, int defer) {
+  __shared__ double s_red[NT / 64];
   if (s->done) return;
   double rznew, rr;
-  sum_partials2(red.partials, nb, rznew, rr, s_red);
+  sum_partials2<NT>(red.partials, nb, rznew, rr, s_red);
   if (threadIdx.x == 0) {
     double pAp = s->pAp;
     s->alpha = (pAp > 0.0) ? s->rz / pAp : 0.0;
@@ -378,8 +394,7 @@ int launch_pcg_update(T *x, T *r, const T *p, T *Ap, const T *d, PcgDev *s, int6
   const int nb = grid_for_u(n);
   hipLaunchKernelGGL(k_pcg_update<T>, dim3(nb), dim3(NTV), 0, st, x, r, p, Ap, d, s, n, red2,
                      p_prev);
-  hipLaunchKernelGGL(k_pcg_update_fin, dim3(1), dim3(NTF), 0, st, s, red2, nb,
-                     p_prev ? 1 : 0);
+  SDME_FIN(k_pcg_update_fin, nb, st, s, red2, nb, p_prev ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

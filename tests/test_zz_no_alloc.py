@@ -2,9 +2,13 @@
 the library's device-resident scratch array) against sdme_jacobi_pcg with a
 caller workspace, through the C ABI: two calls in a row, the second on a
 smaller mesh, in FP64 and mixed precision; requests beyond the array's size
-are refused.  Iterative results are compared as the parity tests compare
-solves: iteration counts within max(1, 2 %), both at the tolerance, and the
-solutions within a bound set by the tolerance."""
+are refused.  With ordered assembly both entry points run the same kernels in
+the same order, so iteration counts and solutions must agree bit for bit.
+With atomic assembly solves are compared as the parity tests compare them:
+both at the tolerance, solutions within a bound set by it, and iteration
+counts within max(1, 2 %) in FP64; in mixed precision the order of the FP32
+atomic additions changes the count from run to run (231-256 over twelve runs
+of either entry point on the small mesh below), so within 12 %."""
 import numpy as np
 import pytest
 
@@ -18,7 +22,7 @@ pytestmark = pytest.mark.gpu
 RTOL = 1e-10
 
 
-def _solve_both(p, prec, seed, shift):
+def _solve_both(p, prec, seed, shift, ordered):
     ud = p.dev(p.mask * p.rand(seed, 1e-3))
     b = p.dev(inputs.uniform(seed + 1, p.N, -1, 1))
     x_ref, x_na = p.zeros(), p.zeros()
@@ -27,27 +31,30 @@ def _solve_both(p, prec, seed, shift):
                                         rtol=RTOL)
     assert rc == 0 and s_na["status"] == 0
     it_r, it_n = s_ref["iterations"], s_na["iterations"]
-    # FP64: the parity bar for iteration counts.  Mixed: the order of the FP32
-    # atomic additions in the operator changes the rounding of the FP32
-    # recursion from run to run, and with it the count by a few percent
-    # (also between two calls of the same entry point)
-    tol = max(1, 0.02 * it_r) if prec == FP64 else max(2, 0.05 * it_r)
-    assert abs(it_r - it_n) <= tol, (it_r, it_n)
     assert s_ref["rel_residual"] <= RTOL and s_na["rel_residual"] <= RTOL
     xr, xn = p.host(x_ref), p.host(x_na)
-    assert np.abs(xn - xr).max() <= 1e-6 * np.abs(xr).max()
+    if ordered:
+        assert it_r == it_n and s_ref["outer"] == s_na["outer"]
+        assert np.array_equal(xr.view(np.uint64), xn.view(np.uint64))
+    else:
+        tol = max(1, 0.02 * it_r) if prec == FP64 else max(2, 0.12 * it_r)
+        assert abs(it_r - it_n) <= tol, (it_r, it_n)
+        assert np.abs(xn - xr).max() <= 1e-6 * np.abs(xr).max()
     return it_n
 
 
-@pytest.mark.parametrize("prec", [FP64, FP32])
-def test_noalloc_pcg_matches_workspace_pcg_two_calls(prec):
-    big = Pair((6, 3, 3), (1.0, 0.5, 0.5), 3, kind=ob.SDME_H, dirichlet=inputs.face_bits(0))
-    small = Pair((3, 2, 2), (0.5, 0.5, 0.5), 2, kind=ob.SDME_M, dirichlet=inputs.face_bits(4))
+@pytest.mark.parametrize("ordered", [False, True], ids=["atomic", "ordered"])
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "mixed"])
+def test_noalloc_pcg_matches_workspace_pcg_two_calls(prec, ordered):
+    big = Pair((6, 3, 3), (1.0, 0.5, 0.5), 3, kind=ob.SDME_H, dirichlet=inputs.face_bits(0),
+               ordered=ordered)
+    small = Pair((3, 2, 2), (0.5, 0.5, 0.5), 2, kind=ob.SDME_M, dirichlet=inputs.face_bits(4),
+                 ordered=ordered)
     assert small.N < big.N
-    assert _solve_both(big, prec, 31, 0.0) > 10
+    assert _solve_both(big, prec, 31, 0.0, ordered) > 10
     # second call: smaller input, the scratch array still holds the first
     # call's contents
-    assert _solve_both(small, prec, 41, 50.0) > 5
+    assert _solve_both(small, prec, 41, 50.0, ordered) > 5
 
 
 def test_noalloc_pcg_refuses_oversized_workspace():
