@@ -214,7 +214,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_init(const T *__restrict__ r, const
 }
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pcg_init_fin(PcgDev *s, double rtol, int maxit,
-                                                      double delta, Reduce red, int nb) {
+                                                     double delta, Reduce red, int nb) {
   __shared__ double s_red[NT / 64];
   double rz, rr;
   sum_partials2<NT>(red.partials, nb, rz, rr, s_red);
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(NTV) void k_pcg_replace(float *__restrict__ r32,
 }
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pcg_replace_fin(PcgDev *s, double delta, Reduce red,
-                                                         int nb) {
+                                                        int nb) {
   __shared__ double s_red[NT / 64];
   double rz, rr;
   sum_partials2<NT>(red.partials, nb, rz, rr, s_red);
